@@ -1,0 +1,96 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module draws random numbers and nothing else: it holds none of the
+solver's arithmetic (no assembly, no stencil, no preconditioner, no PCG).
+Every coefficient realization is a cell array of shape (L, L, L), float64,
+C order with the first lattice index slowest (the big-endian convention of
+the paper's Section 3.2), one value per unit cell G_s of the checkerboard
+(Section 3.1: the coefficient is piecewise constant on the L^3 unit cells).
+
+The named workloads mirror the paper's 3D experiments (Section 5.2, Table 3:
+n0 = 4 grid intervals per cell edge, L up to 128) with the value laws of the
+benchmark configurations:
+
+  c1  L=4,   n0=4, a in {1, 10} with P(10) = 1/2, seed 1, corrector e_1, R = 4
+  c2  L=32,  n0=4, a ~ U[1, 10],                  seed 2, correctors e_1..e_3
+  c3  L=64,  n0=4, a in {1, 100} with P(100) = 1/2, seed 3, correctors e_1..e_3
+  c4  96 realizations, L cycling over {8, 12, 16, 24}, a = exp(N(0, 1)),
+      seeds SeedSequence(4).spawn(96)
+  c5  L=128, n0=4, a = exp(N(0, 1.5^2)),           seed 5
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "cells_bernoulli",
+    "cells_uniform",
+    "cells_lognormal",
+    "random_field",
+    "CONFIGS",
+    "config_cells",
+    "batched_realizations",
+]
+
+
+def _rng(seed) -> np.random.Generator:
+    if isinstance(seed, np.random.SeedSequence):
+        return np.random.default_rng(seed)
+    return np.random.default_rng(np.random.SeedSequence(seed))
+
+
+def cells_bernoulli(L: int, lo: float, hi: float, p: float, seed) -> np.ndarray:
+    """i.i.d. two-valued cells: hi with probability p, lo otherwise."""
+    g = _rng(seed)
+    u = g.random((L, L, L))
+    return np.where(u < p, float(hi), float(lo)).astype(np.float64)
+
+
+def cells_uniform(L: int, lo: float, hi: float, seed) -> np.ndarray:
+    """i.i.d. cells uniform on [lo, hi)."""
+    g = _rng(seed)
+    return (lo + (hi - lo) * g.random((L, L, L))).astype(np.float64)
+
+
+def cells_lognormal(L: int, sigma: float, seed, mu: float = 0.0) -> np.ndarray:
+    """i.i.d. cells exp(N(mu, sigma^2))."""
+    g = _rng(seed)
+    return np.exp(mu + sigma * g.standard_normal((L, L, L))).astype(np.float64)
+
+
+def random_field(N: int, seed, dims: int = 3) -> np.ndarray:
+    """Standard-normal nodal field of shape (N,)*dims (test vectors)."""
+    g = _rng(seed)
+    return g.standard_normal((N,) * dims).astype(np.float64)
+
+
+CONFIGS = {
+    "c1": dict(L=4, n0=4, law="bernoulli", lo=1.0, hi=10.0, p=0.5, seed=1,
+               rank=4, eps=1e-3, tol=1e-8, rhs=(1,), precision="fp64"),
+    "c2": dict(L=32, n0=4, law="uniform", lo=1.0, hi=10.0, seed=2,
+               rank=0, eps=1e-3, tol=1e-8, rhs=(1, 2, 3), precision="fp64"),
+    "c3": dict(L=64, n0=4, law="bernoulli", lo=1.0, hi=100.0, p=0.5, seed=3,
+               rank=0, eps=1e-3, tol=1e-8, rhs=(1, 2, 3), precision="mixed_bf16"),
+    "c5": dict(L=128, n0=4, law="lognormal", sigma=1.5, seed=5,
+               rank=0, eps=1e-3, tol=1e-8, rhs=(1, 2, 3), precision="mixed_bf16"),
+}
+
+
+def config_cells(name: str) -> np.ndarray:
+    """Cell array of a named single-realization workload."""
+    c = CONFIGS[name]
+    if c["law"] == "bernoulli":
+        return cells_bernoulli(c["L"], c["lo"], c["hi"], c["p"], c["seed"])
+    if c["law"] == "uniform":
+        return cells_uniform(c["L"], c["lo"], c["hi"], c["seed"])
+    if c["law"] == "lognormal":
+        return cells_lognormal(c["L"], c["sigma"], c["seed"])
+    raise KeyError(c["law"])
+
+
+def batched_realizations(count: int = 96, sizes=(8, 12, 16, 24), sigma: float = 1.0,
+                         seed: int = 4):
+    """Realizations with uneven L cycling over `sizes`, log-normal cells."""
+    children = np.random.SeedSequence(seed).spawn(count)
+    return [cells_lognormal(sizes[m % len(sizes)], sigma, children[m]) for m in range(count)]
