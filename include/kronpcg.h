@@ -1,0 +1,246 @@
+/*
+ * kronpcg.h - C ABI of the MI355X (gfx950) solver for the periodic 3D
+ * elliptic problem -div(a grad u) = f with a random checkerboard coefficient,
+ * preconditioned by a low-Kronecker-rank approximation of the periodic
+ * Laplacian pseudo-inverse.
+ *
+ * Method: Khoromskaia & Khoromskij, "Tensor-based techniques for fast
+ * discretization and solution of 3D elliptic equations with random
+ * coefficients" (arXiv:2007.06524).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an int status: KP_OK (0), a warning (> 0) or an error
+ *    (< 0).  After an error, kp_last_error() returns a message for the calling
+ *    thread.
+ *  - Grid: the unit cube carries L^3 unit cells with n0 grid intervals per cell
+ *    edge, N = n0*L distinct periodic nodes per axis, h = 1/N (Section 3.1; the
+ *    paper's n1 = N + 1 counts the periodic image of node 0 as well).
+ *  - Layout: every N^3 field is a dense C-order array [i1][i2][i3] with i3
+ *    fastest, i.e. the big-endian multi-index map of Section 3.2.  Cell arrays
+ *    are [c1][c2][c3] of L^3 doubles in the same order.
+ *  - "host" pointers are ordinary CPU memory, copied during the call; the
+ *    caller keeps ownership.  "device" pointers are GPU memory on the
+ *    context's device, owned by the caller, and must stay valid until the
+ *    call's work on the context stream has completed.
+ *  - All GPU work is ordered on the context's stream.  Calls that return host
+ *    results (stats, info, ahom) synchronize that stream before returning.
+ *  - Opaque handles (kp_context, kp_coeff, kp_precond) are owned by the
+ *    library and released with the matching kp_*_destroy / kp_free_* call.
+ */
+#ifndef KRONPCG_H
+#define KRONPCG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kp_context kp_context;
+typedef struct kp_coeff kp_coeff;
+typedef struct kp_precond kp_precond;
+
+enum kp_status {
+  KP_OK = 0,
+  KP_NOT_CONVERGED = 1,        /* maxit reached; x and stats are valid          */
+  KP_WARN_RHS_MEAN = 2,        /* f had a nonzero mean, which was projected out */
+  KP_ERR_ARG = -1,             /* invalid argument (pointer, size, value)       */
+  KP_ERR_HIP = -2,             /* a HIP runtime call failed                     */
+  KP_ERR_NOMEM = -3,           /* device allocation failed                      */
+  KP_ERR_BREAKDOWN = -4,       /* PCG breakdown: <p,Kp> <= 0, <r,z> <= 0 or NaN */
+  KP_ERR_PRECOND_INDEFINITE = -5, /* low-rank symbol not positive on all modes  */
+  KP_ERR_STATE = -6            /* handles from different contexts / sizes       */
+};
+
+/* Arithmetic of the solve.
+ * KP_FP64: stencil, preconditioner (FP64 MFMA) and vectors in double.
+ * KP_MIXED_BF16 / KP_MIXED_FP16: stencil and PCG vectors in float, the three
+ *   preconditioner mode products on BF16 / FP16 MFMA with float accumulation,
+ *   flexible (Polak-Ribiere) PCG; x, all dot products, norms and the zero-mean
+ *   projection stay in double, and the residual is periodically replaced by
+ *   the true residual f - K x computed in double from double weights. */
+enum kp_precision { KP_FP64 = 0, KP_MIXED_BF16 = 1, KP_MIXED_FP16 = 2 };
+
+typedef struct {
+  int rank;              /* canonical rank R actually used                    */
+  int tucker_rank;       /* Tucker rank r_T of the weighted symbol            */
+  int source;            /* 0: ALS-refined Tucker-to-canonical, 1: Laplace quadrature */
+  int pad_;
+  double cp_rel_err;     /* ||B - CP|| / ||B|| of the Tucker core fit         */
+  double quad_rel_err;   /* max relative error of the Laplace quadrature      */
+  double rho_min;        /* min over nonzero modes of G_R / G+                */
+  double rho_max;        /* max over nonzero modes of G_R / G+                */
+  double cancellation;   /* sum_k |u1||u2||u3| / ||G_R||  (1 = none)          */
+  double build_ms;       /* host time of the construction                     */
+} kp_precond_info;
+
+typedef struct {
+  double tol;            /* stop when ||f - K x||_2 <= tol ||f||_2 (true residual); default 1e-8 */
+  int maxit;             /* iteration cap; default 2000                                 */
+  int replace_every;     /* mixed precision: true-residual replacement period; 0 = never (default 25 mixed, 0 FP64) */
+  int use_x0;            /* 1: start from the contents of x; 0: start from x = 0       */
+  int check_every;       /* iterations queued between host convergence checks; 0 = auto */
+} kp_solve_opts;
+
+typedef struct {
+  int iters;             /* PCG iterations performed                          */
+  int replacements;      /* true-residual replacements performed              */
+  double relres_true;    /* ||f - K x|| / ||f|| in double at exit             */
+  double relres_rec;     /* recursive residual ratio at exit                  */
+  double rhs_mean;       /* mean removed from f                               */
+  double ms;             /* wall time of the solve on the stream (hipEvents)  */
+} kp_solve_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL selects the null stream).  *out receives the handle. */
+int kp_context_create(int device, void* hip_stream, kp_context** out);
+
+/* Replace the stream used by later calls. */
+int kp_context_set_stream(kp_context* ctx, void* hip_stream);
+
+/* Route the library's device allocations through caller callbacks (for
+ * example a caching allocator).  alloc(bytes, user) returns device memory or
+ * NULL; release(ptr, user) frees it.  Pass NULL callbacks to go back to
+ * hipMalloc / hipFree.  Only affects allocations made after the call. */
+int kp_context_set_allocator(kp_context* ctx, void* (*alloc)(size_t bytes, void* user),
+                             void (*release)(void* ptr, void* user), void* user);
+
+int kp_context_destroy(kp_context* ctx);
+
+/* Per-kernel-class timing with HIP events recorded on the context stream
+ * around every launch of the class (the paper reports matrix generation,
+ * right-hand side and solver times, Tables 1-3; this splits the solver).
+ * Enabling clears the accumulators; reading synchronizes the stream.
+ * ms and launches are host arrays of KP_TIMER_COUNT entries. */
+enum kp_timer {
+  KP_TIMER_STENCIL = 0,     /* 7-point stencil q = K p inside the iteration      */
+  KP_TIMER_GEMM_MODE3 = 1,  /* preconditioner GEMM contracting i3 (first stage)  */
+  KP_TIMER_GEMM_MODE2 = 2,  /* preconditioner GEMM contracting i2 (second stage) */
+  KP_TIMER_GEMM_MODE1 = 3,  /* preconditioner GEMM contracting (k, i1) (third)   */
+  KP_TIMER_VECTOR = 4,      /* vector updates, casts, reductions, finalize       */
+  KP_TIMER_ASSEMBLE = 5,    /* assembly of weights and right-hand sides          */
+  KP_TIMER_RESIDUAL = 6,    /* true residual f - K x in double                   */
+  KP_TIMER_COUNT = 7
+};
+int kp_context_set_timing(kp_context* ctx, int enable);
+int kp_context_read_timing(kp_context* ctx, double* ms, long long* launches);
+
+/* ---- assembly (Sections 3.1-3.3) ---------------------------------------- */
+
+/* Assemble the stiffness and the three corrector right-hand sides of one
+ * coefficient realization (the paper's "matr." and "RHS" steps).
+ *   a_cell: host, L^3 doubles, [c1][c2][c3]; each value finite and > 0
+ *           (the checkerboard coefficient lambda + beta * a_hat of eq.
+ *           coef_diag, one value per unit cell).
+ *   L >= 1, n0 >= 1, N = n0*L >= 2.
+ * The stiffness is the Kronecker sum of eq. As_Kron_d: per cell a_c times the
+ * 1D Neumann Laplacian in one direction and the lumped half-weight identity
+ * diag(1/2,1,...,1,1/2) in the others, wrapped periodically.  It is stored as
+ * the three edge-weight fields w_l(p) = weight of the edge (p, p+e_l) (the
+ * mean of the coefficient over the four voxels sharing that edge), in double
+ * and, for mixed precision, also in float.  The corrector right-hand sides of
+ * eq. FEM_discr_RHS are f_i(p) = h (w_i(p) - w_i(p - e_i)) for the operator
+ * K = A / h, in double.  Errors: KP_ERR_ARG on bad sizes or a non-finite or
+ * non-positive cell. */
+int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precision,
+                kp_coeff** out);
+
+/* Copy the assembled fields into caller device buffers (either may be NULL):
+ *   w_dev: 3*N^3 doubles [l][i1][i2][i3];  f_dev: 3*N^3 doubles [i-1][i1][i2][i3]. */
+int kp_coeff_fields(kp_context* ctx, const kp_coeff* coeff, double* w_dev, double* f_dev);
+
+/* Re-assemble an existing coefficient from a new realization whose cells are
+ * already in device memory (a_cell_dev: L^3 doubles, same L and n0 as at
+ * setup_coeff), as for a long sequence of stochastic realizations.  The cells
+ * are validated on the device (finite, > 0; else KP_ERR_ARG, and the
+ * coefficient keeps its previous fields).  Synchronizes the stream. */
+int kp_coeff_update(kp_context* ctx, kp_coeff* coeff, const double* a_cell_dev);
+
+/* Grid size N of an assembled coefficient (or -1 for NULL). */
+int kp_coeff_size(const kp_coeff* coeff);
+
+int kp_free_coeff(kp_coeff* coeff);
+
+/* q = K p for the assembled stiffness (eq. FEM_matrix with the Kronecker-sum
+ * stiffness, 7-point form), p and q device arrays of N^3 doubles.  With
+ * precision KP_FP64 the operator runs in double; with a mixed precision it
+ * runs the float stencil on float weights (inputs rounded to float, output
+ * widened to double). */
+int kp_stiffness_apply(kp_context* ctx, const kp_coeff* coeff, int precision,
+                       const double* p_dev, double* q_dev);
+
+/* ---- preconditioner (Section 4.2) --------------------------------------- */
+
+/* Canonical factors of the low-rank preconditioner symbol, on the host only
+ * (no GPU work).  The symbol G+ of eq. 3a (1/(mu_i+mu_j+mu_k),
+ * mu_k = 4 sin^2(pi k/N)) is approximated by G_R = sum_k u1^(k) x u2^(k) x u3^(k):
+ * Tucker decomposition of the relatively weighted symbol followed by a
+ * Tucker-to-canonical ALS of its core, initialized from a quadrature of the
+ * Laplace transform 1/x = int exp(-xt) dt (Lemma RankPinverse).
+ *   eps:  Tucker truncation tolerance (relative Frobenius); with rank = 0
+ *         also the target of the core fit that selects R.
+ *   rank: R > 0 fixes the rank (1..16); 0 selects it from eps.
+ *   factors_out: host, capacity doubles, receives 3*R*N values [l][k][i].
+ * Errors: KP_ERR_ARG (N < 2, eps not in (0,1), rank > 16, capacity too small),
+ * KP_ERR_PRECOND_INDEFINITE when min G_R/G+ <= 0. */
+int kp_lowrank_factors(int N, double eps, int rank, double* factors_out, size_t capacity,
+                       kp_precond_info* info);
+
+/* Build the preconditioner for grid size N: the canonical factors of
+ * kp_lowrank_factors, turned into the dense N x N circulants
+ * C_l^(k) = F* diag(u_l^(k)) F (real symmetric, eq. Lap3DtimesX) and
+ * uploaded in the layout of the mode-product GEMMs.  info may be NULL. */
+int build_preconditioner(kp_context* ctx, int N, double eps, int rank, int precision,
+                         kp_precond** out, kp_precond_info* info);
+
+/* Same, from caller-supplied canonical factors: factors is host memory of
+ * 3*R*N doubles [l][k][i], each u_l^(k) even (u(i) = u(N-i)), 1 <= R <= 16. */
+int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors,
+                            int precision, kp_precond** out);
+
+/* Rank R of a preconditioner (or -1 for NULL). */
+int kp_precond_rank(const kp_precond* pc);
+
+/* z = sum_k (C1^(k) x C2^(k) x C3^(k)) r (eq. Lap3DtimesX), as three MFMA
+ * mode-product GEMMs, r and z device arrays of N^3 doubles.  No zero-mean
+ * projection is applied.  In a mixed precision, r is rounded to BF16/FP16
+ * and the result (float accumulation) is widened to double. */
+int kp_precond_apply(kp_context* ctx, const kp_precond* pc, const double* r_dev, double* z_dev);
+
+int kp_free_precond(kp_precond* pc);
+
+/* ---- solve (Section 4.1) ------------------------------------------------ */
+
+/* Solve K x = f on the subspace <x,1> = 0 (eq. DD_Eqn) by PCG preconditioned
+ * with the low-rank pseudo-inverse (eq. PCG_DD_Eqn).
+ *   rhs:   1..3 selects the assembled corrector right-hand side f_rhs;
+ *          0 uses f_dev (device, N^3 doubles), projected to zero mean.
+ *   x_dev: device, N^3 doubles, caller-owned; read as the initial guess when
+ *          opts->use_x0, always overwritten with the zero-mean solution.
+ *   opts:  may be NULL for the defaults; stats may be NULL.
+ * The precision of the solve is the coefficient's; a mixed coefficient needs a
+ * preconditioner of a mixed precision and vice versa (else KP_ERR_STATE).
+ * Returns KP_OK, KP_NOT_CONVERGED, KP_WARN_RHS_MEAN (when the removed mean of
+ * a user f exceeds 1e-12 ||f|| / sqrt(N^3)), or an error.  ||f|| = 0 gives
+ * x = 0 and 0 iterations. */
+int pcg_solve(kp_context* ctx, const kp_coeff* coeff, const kp_precond* pc, int rhs,
+              const double* f_dev, double* x_dev, const kp_solve_opts* opts,
+              kp_solve_stats* stats);
+
+/* Homogenized matrix of one realization (eq. Ahom3_m_entry_comp):
+ *   ahom[i][j] = delta_ij mean(a) - h sum_p phi_i(p) f_j(p),  i,j = 1..3,
+ * where phi_dev[i] (device, N^3 doubles) solves corrector i+1.  ahom is host
+ * memory of 9 doubles, row-major.  No symmetrization is applied. */
+int kp_homogenized_matrix(kp_context* ctx, const kp_coeff* coeff, const double* const* phi_dev,
+                          double* ahom);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* kp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRONPCG_H */

@@ -1,0 +1,239 @@
+"""kronpcg: periodic 3D checkerboard PCG solver with a low-Kronecker-rank
+preconditioner on MI355X (gfx950).
+
+Python binding of the C ABI in include/kronpcg.h.  PyTorch supplies device
+memory (its caching allocator backs the library's allocations) and streams;
+every step of the solve runs in the library's HIP kernels.  There is no CPU
+fallback: without the built library or a GPU the calls raise.
+
+Method: Khoromskaia & Khoromskij, arXiv:2007.06524 (assembly, Section 3;
+preconditioner, Section 4.2; PCG, Section 4.1; homogenized matrix, Section 3.4).
+"""
+
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import weakref
+
+import numpy as np
+
+from . import _lib
+from ._lib import (KP_FP64, KP_MIXED_BF16, KP_MIXED_FP16, KP_NOT_CONVERGED, KP_OK,
+                   KP_WARN_RHS_MEAN, PRECISIONS, KronPCGError, PrecondInfo, SolveOpts, SolveStats,
+                   check, load)
+
+__all__ = ["Context", "Coeff", "Precond", "solve", "homogenized_matrix", "stiffness_apply",
+           "lowrank_factors", "KronPCGError", "PRECISIONS", "KP_FP64", "KP_MIXED_BF16",
+           "KP_MIXED_FP16", "KP_OK", "KP_NOT_CONVERGED", "KP_WARN_RHS_MEAN"]
+
+_live_contexts = weakref.WeakSet()
+
+
+def _precision(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _ptr(t) -> C.c_void_p:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Device, stream and allocator of the library (kp_context)."""
+
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+        import torch
+        lib = load()
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        check(lib.kp_context_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+        self._cb = None
+        if torch_allocator:
+            dev, strm = device, self.stream
+
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm)
+                except Exception:
+                    return None
+
+            def _release(ptr, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._cb = (_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
+            check(lib.kp_context_set_allocator(h, self._cb[0], self._cb[1], None))
+        self._owned = []
+        _live_contexts.add(self)
+
+    def set_timing(self, enable: bool = True):
+        """Start (and clear) or stop per-kernel-class HIP event timing."""
+        check(load().kp_context_set_timing(self.handle, int(bool(enable))))
+
+    def read_timing(self):
+        """{class: (total ms, launches)} accumulated since set_timing(True)."""
+        n = len(_lib.TIMERS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_longlong * n)()
+        check(load().kp_context_read_timing(self.handle, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.TIMERS)}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            for obj in list(self._owned):
+                obj.free()
+            load().kp_context_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+@atexit.register
+def _close_all():
+    for ctx in list(_live_contexts):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+
+
+class Coeff:
+    """An assembled coefficient realization (setup_coeff): weights and correctors' RHS."""
+
+    def __init__(self, ctx: Context, cells: np.ndarray, n0: int, precision="fp64"):
+        cells = np.ascontiguousarray(cells, dtype=np.float64)
+        if cells.ndim != 3 or len(set(cells.shape)) != 1:
+            raise ValueError("cells must be an (L, L, L) array")
+        self.ctx = ctx
+        self.L = cells.shape[0]
+        self.n0 = int(n0)
+        self.precision = _precision(precision)
+        h = C.c_void_p()
+        check(load().setup_coeff(ctx.handle, self.L, self.n0,
+                                 cells.ctypes.data_as(C.POINTER(C.c_double)), self.precision, C.byref(h)))
+        self.handle = h
+        self.N = self.L * self.n0
+        ctx._owned.append(self)
+
+    def update(self, cells_dev):
+        """Re-assemble from a new realization already on the device (float64 (L, L, L))."""
+        import torch
+        if tuple(cells_dev.shape) != (self.L,) * 3:
+            raise ValueError("cells_dev must have shape (L, L, L)")
+        check(load().kp_coeff_update(self.ctx.handle, self.handle, _ptr(cells_dev)))
+
+    def fields(self):
+        """(w, f): torch float64 tensors of shape (3, N, N, N)."""
+        import torch
+        N = self.N
+        w = torch.empty((3, N, N, N), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        f = torch.empty_like(w)
+        check(load().kp_coeff_fields(self.ctx.handle, self.handle, _ptr(w), _ptr(f)))
+        return w, f
+
+    def free(self):
+        if self.handle is not None:
+            load().kp_free_coeff(self.handle)
+            self.handle = None
+            if self in self.ctx._owned:
+                self.ctx._owned.remove(self)
+
+
+class Precond:
+    """Low-rank preconditioner (build_preconditioner / kp_precond_from_factors)."""
+
+    def __init__(self, ctx: Context, N: int, eps: float = 1e-3, rank: int = 0, precision="fp64",
+                 factors: np.ndarray | None = None):
+        self.ctx = ctx
+        self.N = int(N)
+        self.precision = _precision(precision)
+        h = C.c_void_p()
+        lib = load()
+        if factors is None:
+            info = PrecondInfo()
+            check(lib.build_preconditioner(ctx.handle, self.N, float(eps), int(rank), self.precision,
+                                           C.byref(h), C.byref(info)))
+            self.info = info.as_dict()
+        else:
+            F = np.ascontiguousarray(factors, dtype=np.float64)
+            if F.ndim != 3 or F.shape[0] != 3 or F.shape[2] != self.N:
+                raise ValueError("factors must have shape (3, R, N)")
+            check(lib.kp_precond_from_factors(ctx.handle, self.N, F.shape[1],
+                                              F.ctypes.data_as(C.POINTER(C.c_double)), self.precision,
+                                              C.byref(h)))
+            self.info = {"rank": F.shape[1]}
+        self.handle = h
+        self.R = lib.kp_precond_rank(h)
+        ctx._owned.append(self)
+
+    def apply(self, r):
+        """z = sum_k (C1^k x C2^k x C3^k) r, r a float64 CUDA tensor (N, N, N)."""
+        import torch
+        z = torch.empty_like(r)
+        check(load().kp_precond_apply(self.ctx.handle, self.handle, _ptr(r), _ptr(z)))
+        return z
+
+    def free(self):
+        if self.handle is not None:
+            load().kp_free_precond(self.handle)
+            self.handle = None
+            if self in self.ctx._owned:
+                self.ctx._owned.remove(self)
+
+
+def stiffness_apply(ctx: Context, coeff: Coeff, p, precision=None):
+    """q = K p for the assembled stiffness (float64 CUDA tensors)."""
+    import torch
+    q = torch.empty_like(p)
+    prec = coeff.precision if precision is None else _precision(precision)
+    check(load().kp_stiffness_apply(ctx.handle, coeff.handle, prec, _ptr(p), _ptr(q)))
+    return q
+
+
+def solve(ctx: Context, coeff: Coeff, precond: Precond, rhs: int = 1, f=None, x=None,
+          tol: float = 1e-8, maxit: int = 2000, replace_every: int | None = None,
+          use_x0: bool = False, check_every: int = 0):
+    """pcg_solve: returns (x, stats dict, status)."""
+    import torch
+    N = coeff.N
+    if x is None:
+        x = torch.empty((N, N, N), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    if replace_every is None:
+        replace_every = 0 if coeff.precision == KP_FP64 else 25
+    opts = SolveOpts(float(tol), int(maxit), int(replace_every), int(bool(use_x0)), int(check_every))
+    stats = SolveStats()
+    fp = _ptr(f) if f is not None else None
+    st = load().pcg_solve(ctx.handle, coeff.handle, precond.handle, int(rhs), fp, _ptr(x),
+                          C.byref(opts), C.byref(stats))
+    check(st, allow=(KP_OK, KP_NOT_CONVERGED, KP_WARN_RHS_MEAN))
+    return x, stats.as_dict(), st
+
+
+def homogenized_matrix(ctx: Context, coeff: Coeff, phis) -> np.ndarray:
+    """kp_homogenized_matrix: 3x3 numpy array from the three corrector solutions."""
+    arr = (C.c_void_p * 3)(*[_ptr(p).value for p in phis])
+    out = (C.c_double * 9)()
+    check(load().kp_homogenized_matrix(ctx.handle, coeff.handle, arr, out))
+    return np.array(list(out)).reshape(3, 3)
+
+
+def lowrank_factors(N: int, eps: float = 1e-3, rank: int = 0):
+    """kp_lowrank_factors (host only): canonical factors (3, R, N) and the report."""
+    cap = 3 * 16 * N
+    buf = (C.c_double * cap)()
+    info = PrecondInfo()
+    check(load().kp_lowrank_factors(int(N), float(eps), int(rank), buf, cap, C.byref(info)))
+    R = info.rank
+    F = np.frombuffer(buf, dtype=np.float64, count=3 * R * N).reshape(3, R, N).copy()
+    return F, info.as_dict()

@@ -1,0 +1,404 @@
+// Vector updates and reductions of the PCG iteration.
+//
+// Every reduction is deterministic: each block accumulates a fixed grid-stride
+// subset in double, reduces it with 64-lane wavefront shuffles and LDS, and
+// writes one partial; a one-block finalize kernel adds the partials in a fixed
+// order and updates the PCG scalars on the device, so the iteration never
+// waits for the host.
+
+#include <cmath>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of NV values over a 256-thread block, written to out[v * stride].
+template <int NV>
+__device__ __forceinline__ void block_sums_store(double (&v)[NV], double* out, size_t stride) {
+  __shared__ double red[NV][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) red[k][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int k = threadIdx.x;
+    out[k * stride] = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
+  }
+}
+
+__device__ __forceinline__ bf16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16_t f32_to_f16_rne(float x) {
+  _Float16 hv = (_Float16)x;  // IEEE round to nearest even
+  return __builtin_bit_cast(bf16_t, hv);
+}
+
+__device__ __forceinline__ bf16_t to16(float x, int fp16) {
+  return fp16 ? f32_to_f16_rne(x) : f32_to_bf16_rne(x);
+}
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// One block of 256 threads: totals of nvals values, then the PCG scalar logic.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int nparts,
+                                                  int nvals, int mode, Scalars* s, double n3) {
+  if (s->done && mode != FIN_SUM && mode != FIN_FF) return;
+  __shared__ double tot[8];
+  for (int v = 0; v < nvals; ++v) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) acc += partial[(size_t)v * nparts + i];
+    __shared__ double red[4];
+    acc = wave_sum(acc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) tot[v] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  for (int v = 0; v < nvals; ++v) s->sums[v] = tot[v];
+  switch (mode) {
+    case FIN_SUM:
+      break;
+    case FIN_FF:  // partials of k_sum2: (sum, sum of squares)
+      s->ff = tot[1];
+      break;
+    case FIN_ALPHA: {
+      const double pq = tot[0];
+      s->pq = pq;
+      s->x16_scale = s->x16_scale_next;  // r of this iteration is rounded with this scale
+      if (!(pq > 0.0) || !finite(pq)) {
+        s->breakdown = 1;
+        s->done = 1;
+        s->alpha = 0.0;
+      } else {
+        s->alpha = s->rho / pq;
+      }
+      break;
+    }
+    case FIN_RR:
+    case FIN_RR_NOCOUNT: {
+      const double rr = tot[0];
+      s->rr = rr;
+      if (mode == FIN_RR) s->iters += 1;
+      // Power of two bringing the RMS of r near 1 before 16-bit rounding (keeps
+      // FP16 inputs normal as the residual shrinks; exact to undo).
+      double sc = 1.0;
+      if (rr > 0.0 && finite(rr)) {
+        double e = rint(-0.5 * log2(rr / n3));
+        e = fmin(fmax(e, -120.0), 120.0);
+        sc = exp2(e);
+      }
+      s->x16_scale_next = sc;
+      if (mode == FIN_RR_NOCOUNT) s->x16_scale = sc;  // followed by a fresh conversion
+      if (!finite(rr)) {
+        s->breakdown = 1;
+        s->done = 1;
+      } else if (rr <= s->tol2ff) {
+        s->done = 1;
+      }
+      break;
+    }
+    case FIN_PREC:
+    case FIN_PREC_FR:
+    case FIN_PREC_INIT: {
+      // tot: <r,z>, <q,z>, sum z, sum r, sum q
+      const double mz = tot[2] / n3;
+      const double rho_new = tot[0] - mz * tot[3];
+      s->mz = mz;
+      if (!(rho_new > 0.0) || !finite(rho_new)) {
+        s->breakdown = 1;
+        s->done = 1;
+        break;
+      }
+      if (mode == FIN_PREC_INIT) {
+        s->beta = 0.0;
+      } else if (s->flexible && mode == FIN_PREC) {
+        // <z - mz, r_new - r_old> = -alpha <z - mz, q>
+        s->beta = -s->alpha * (tot[1] - mz * tot[4]) / s->rho;
+      } else {
+        s->beta = rho_new / s->rho;
+      }
+      s->rho = rho_new;
+      break;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, const T* __restrict__ p,
+                                                   T* __restrict__ r, const T* __restrict__ q,
+                                                   bf16_t* __restrict__ r16, int fp16,
+                                                   const Scalars* __restrict__ s,
+                                                   double* __restrict__ partial, size_t n) {
+  if (s->done) return;
+  const double alpha = s->alpha;
+  const T ta = (T)alpha;
+  const float sc = (float)s->x16_scale;
+  double acc[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const T pi = p[i];
+    x[i] += alpha * (double)pi;
+    const T rn = r[i] - ta * q[i];
+    r[i] = rn;
+    if (r16) r16[i] = to16((float)rn * sc, fp16);
+    acc[0] += (double)rn * (double)rn;
+  }
+  block_sums_store<1>(acc, partial + blockIdx.x, gridDim.x);
+}
+
+// <r,z>, <q,z>, sum z, sum r, sum q (q may be null on the first application).
+template <typename T>
+__global__ __launch_bounds__(256) void k_prec_dots(const T* __restrict__ z, const T* __restrict__ r,
+                                                   const T* __restrict__ q,
+                                                   const Scalars* __restrict__ s,
+                                                   double* __restrict__ partial, size_t n) {
+  if (s->done) return;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double zi = (double)z[i], ri = (double)r[i];
+    acc[0] += ri * zi;
+    acc[2] += zi;
+    acc[3] += ri;
+    if (q) {
+      const double qi = (double)q[i];
+      acc[1] += qi * zi;
+      acc[4] += qi;
+    }
+  }
+  block_sums_store<5>(acc, partial + blockIdx.x, gridDim.x);
+}
+
+// p = (z - mean(z)) + beta p
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_p(const T* __restrict__ z, T* __restrict__ p,
+                                                  const Scalars* __restrict__ s, size_t n) {
+  if (s->done) return;
+  const T beta = (T)s->beta;
+  const T mz = (T)s->mz;
+  if (s->beta == 0.0) {  // restart: p may hold stale or uninitialized values
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+      p[i] = z[i] - mz;
+    return;
+  }
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    p[i] = (z[i] - mz) + beta * p[i];
+}
+
+__global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ a, size_t n,
+                                              double* __restrict__ partial) {
+  double acc[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double v = a[i];
+    acc[0] += v;
+    acc[1] += v * v;
+  }
+  block_sums_store<2>(acc, partial + blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_copy_project(const double* __restrict__ f, double mean,
+                                                      double* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    out[i] = f[i] - mean;
+}
+
+__global__ __launch_bounds__(256) void k_cast_f64_f32(const double* __restrict__ a,
+                                                      float* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    b[i] = (float)a[i];
+}
+
+__global__ __launch_bounds__(256) void k_cast_f32_f64(const float* __restrict__ a,
+                                                      double* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    b[i] = (double)a[i];
+}
+
+__global__ __launch_bounds__(256) void k_cast_to16(const double* __restrict__ a,
+                                                   bf16_t* __restrict__ b, size_t n, int fp16) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    b[i] = to16((float)a[i], fp16);
+}
+
+__global__ __launch_bounds__(256) void k_cast32_to16(const float* __restrict__ a,
+                                                     bf16_t* __restrict__ b, size_t n, int fp16,
+                                                     const Scalars* __restrict__ s) {
+  if (s && s->done) return;
+  const float sc = s ? (float)s->x16_scale : 1.0f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    b[i] = to16(a[i] * sc, fp16);
+}
+
+__global__ __launch_bounds__(256) void k_fill(double* __restrict__ a, double v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    a[i] = v;
+}
+
+// Nine dot products <phi_i, f_j> and the sum of the cell values.
+struct PhiPtrs {
+  const double* p[3];
+};
+
+__global__ __launch_bounds__(256) void k_multidot9(PhiPtrs phi, const double* __restrict__ f,
+                                                   size_t n, const double* __restrict__ cells,
+                                                   size_t ncells, double* __restrict__ partial) {
+  double acc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double f0 = f[i], f1 = f[n + i], f2 = f[2 * n + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double v = phi.p[a][i];
+      acc[3 * a + 0] += v * f0;
+      acc[3 * a + 1] += v * f1;
+      acc[3 * a + 2] += v * f2;
+    }
+  }
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < ncells; i += (size_t)gridDim.x * 256)
+    acc[9] += cells[i];
+  block_sums_store<10>(acc, partial + blockIdx.x, gridDim.x);
+}
+
+int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > (size_t)kRedBlocks) b = kRedBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nvals, int mode,
+                    Scalars* s, size_t n3) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, ctx->stream, partial, nparts, nvals, mode,
+                     s, (double)n3);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+template <typename T>
+int launch_update_xr(kp_context* ctx, double* x, const T* p, T* r, const T* q, bf16_t* r16,
+                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  const int g = kRedBlocks;
+  hipLaunchKernelGGL(k_update_xr<T>, dim3(g), dim3(256), 0, ctx->stream, x, p, r, q, r16, fp16, s,
+                     partial, n);
+  KP_HIP(hipGetLastError());
+  *nparts = g;
+  return KP_OK;
+}
+
+template <typename T>
+int launch_prec_dots(kp_context* ctx, const T* z, const T* r, const T* q, const Scalars* s,
+                     double* partial, int* nparts, size_t n) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  const int g = kRedBlocks;
+  hipLaunchKernelGGL(k_prec_dots<T>, dim3(g), dim3(256), 0, ctx->stream, z, r, q, s, partial, n);
+  KP_HIP(hipGetLastError());
+  *nparts = g;
+  return KP_OK;
+}
+
+template <typename T>
+int launch_update_p(kp_context* ctx, const T* z, T* p, const Scalars* s, size_t n) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_update_p<T>, dim3(grid_for(n)), dim3(256), 0, ctx->stream, z, p, s, n);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+template int launch_update_xr<double>(kp_context*, double*, const double*, double*, const double*,
+                                      bf16_t*, int, const Scalars*, double*, int*, size_t);
+template int launch_update_xr<float>(kp_context*, double*, const float*, float*, const float*,
+                                     bf16_t*, int, const Scalars*, double*, int*, size_t);
+template int launch_prec_dots<double>(kp_context*, const double*, const double*, const double*,
+                                      const Scalars*, double*, int*, size_t);
+template int launch_prec_dots<float>(kp_context*, const float*, const float*, const float*,
+                                     const Scalars*, double*, int*, size_t);
+template int launch_update_p<double>(kp_context*, const double*, double*, const Scalars*, size_t);
+template int launch_update_p<float>(kp_context*, const float*, float*, const Scalars*, size_t);
+
+int launch_sum2(kp_context* ctx, const double* a, size_t n, double* partial, int* nparts) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  const int g = kRedBlocks;
+  hipLaunchKernelGGL(k_sum2, dim3(g), dim3(256), 0, ctx->stream, a, n, partial);
+  KP_HIP(hipGetLastError());
+  *nparts = g;
+  return KP_OK;
+}
+
+int launch_copy_project_f(kp_context* ctx, const double* f, double mean, double* out, size_t n) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_copy_project, dim3(grid_for(n)), dim3(256), 0, ctx->stream, f, mean, out, n);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_cast_f64_f32(kp_context* ctx, const double* a, float* b, size_t n) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_cast_f64_f32, dim3(grid_for(n)), dim3(256), 0, ctx->stream, a, b, n);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_cast_f32_f64(kp_context* ctx, const float* a, double* b, size_t n) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_cast_f32_f64, dim3(grid_for(n)), dim3(256), 0, ctx->stream, a, b, n);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_cast_to16(kp_context* ctx, const double* a, bf16_t* b, size_t n, int fp16) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_cast_to16, dim3(grid_for(n)), dim3(256), 0, ctx->stream, a, b, n, fp16);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_cast32_to16(kp_context* ctx, const float* a, bf16_t* b, size_t n, int fp16,
+                       const Scalars* s) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_cast32_to16, dim3(grid_for(n)), dim3(256), 0, ctx->stream, a, b, n, fp16,
+                     s);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_fill_f64(kp_context* ctx, double* a, double v, size_t n) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, ctx->stream, a, v, n);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_multidot9(kp_context* ctx, const double* const* phi, const double* f, size_t n,
+                     const double* cells, size_t ncells, double* partial, int* nparts) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  PhiPtrs pp;
+  for (int a = 0; a < 3; ++a) pp.p[a] = phi[a];
+  const int g = kRedBlocks;
+  hipLaunchKernelGGL(k_multidot9, dim3(g), dim3(256), 0, ctx->stream, pp, f, n, cells, ncells,
+                     partial);
+  KP_HIP(hipGetLastError());
+  *nparts = g;
+  return KP_OK;
+}
+
+}  // namespace kp

@@ -1,0 +1,210 @@
+// Internal declarations of the kronpcg library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "kronpcg.h"
+
+namespace kp {
+
+// Thread-local error message; returns `code` for convenient `return fail(...)`.
+int fail(int code, const char* fmt, ...);
+
+#define KP_HIP(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t kp_e_ = (expr);                                                         \
+    if (kp_e_ != hipSuccess)                                                           \
+      return ::kp::fail(KP_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(kp_e_), \
+                        __FILE__, __LINE__);                                           \
+  } while (0)
+
+#define KP_TRY(expr)             \
+  do {                           \
+    int kp_s_ = (expr);          \
+    if (kp_s_ < 0) return kp_s_; \
+  } while (0)
+
+using bf16_t = uint16_t;  // storage of bfloat16 / float16 values
+
+// PCG scalars kept on the device so that the iteration needs no host round trip.
+struct Scalars {
+  double ff;      // ||f||^2 of the projected right-hand side
+  double tol2ff;  // tol^2 * ||f||^2
+  double rr;      // ||r||^2
+  double rho;     // <r, z - mean(z)>
+  double pq;      // <p, K p>
+  double alpha;
+  double beta;
+  double mz;      // mean of z
+  double x16_scale;       // power of two applied to r before its 16-bit rounding
+  double x16_scale_next;  // the scale for the next conversion (from the newest ||r||)
+  double sums[8]; // scratch results of the last multi-value reduction
+  int done;       // 1: converged (recursive test) or broken down; kernels then no-op
+  int breakdown;  // 1: <p,Kp> <= 0, rho <= 0 or non-finite
+  int iters;      // iterations completed
+  int flexible;   // 1: Polak-Ribiere beta, 0: Fletcher-Reeves beta
+};
+
+// Grow-only device buffer owned by a context.
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Workspace slots of a context.
+enum Slot {
+  WS_R = 0, WS_Z, WS_P, WS_Q,   // PCG vectors (double or float)
+  WS_X16,                       // preconditioner input in BF16/FP16
+  WS_T, WS_U,                   // mode-product intermediates (R N^3 each)
+  WS_PART,                      // reduction partials
+  WS_SCAL,                      // Scalars
+  WS_TMP64,                     // double scratch field (apply entry points)
+  WS_TMP64B,
+  WS_FLAG,                      // one int (cell validation)
+  WS_COUNT
+};
+
+// Reduction modes of the device finalize kernel.
+enum FinMode {
+  FIN_SUM = 0,      // sums[v] = total of value v
+  FIN_ALPHA = 1,    // pq = sum; alpha = rho / pq
+  FIN_RR = 2,       // rr = sum; iteration done; convergence test
+  FIN_RR_NOCOUNT = 3,
+  FIN_PREC = 4,     // sums of <r,z>, <q,z>, sum z, sum r, sum q -> rho, beta, mz
+  FIN_PREC_INIT = 5,// same, beta = 0 (restart)
+  FIN_FF = 6,       // ff = second total (sum of squares from k_sum2)
+  FIN_PREC_FR = 7   // as FIN_PREC with the Fletcher-Reeves beta (after a residual replacement)
+};
+
+struct TimerRec {
+  int id;
+  hipEvent_t a, b;
+};
+
+}  // namespace kp
+
+struct kp_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* user = nullptr;
+  kp::Buffer ws[kp::WS_COUNT];
+  kp::Scalars* host_scal = nullptr;  // pinned mirror of the device scalars
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // per-kernel-class timing (kp_context_set_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<kp::TimerRec> pending;
+  double t_ms[KP_TIMER_COUNT] = {};
+  long long t_count[KP_TIMER_COUNT] = {};
+};
+
+namespace kp {
+
+// Records events around the launches made during its lifetime when timing is on.
+class ScopedTimer {
+ public:
+  ScopedTimer(kp_context* ctx, int id);
+  ~ScopedTimer();
+
+ private:
+  kp_context* ctx_;
+  int id_;
+  hipEvent_t a_ = nullptr;
+};
+
+// Folds completed event pairs into the accumulators (call after a stream sync).
+void resolve_timers(kp_context* ctx);
+
+}  // namespace kp
+
+struct kp_coeff {
+  kp_context* ctx = nullptr;
+  int L = 0, n0 = 0, N = 0;
+  int precision = KP_FP64;
+  double* cells = nullptr;  // L^3
+  double* w64 = nullptr;    // 3 N^3
+  float* w32 = nullptr;     // 3 N^3 (mixed only)
+  double* f = nullptr;      // 3 N^3
+};
+
+struct kp_precond {
+  kp_context* ctx = nullptr;
+  int N = 0, R = 0;
+  int precision = KP_FP64;
+  // Circulant operands of the three NT GEMMs (see precond.hip for the layouts).
+  double* a1_64 = nullptr;  // [j1][(k,i1)]     = C1^k[j1][i1]     N x RN
+  double* c2_64 = nullptr;  // [k][j2][i2]      = C2^k[j2][i2]     R x N x N
+  double* b3_64 = nullptr;  // [(k,j3)][i3]     = C3^k[j3][i3]     RN x N
+  // 16-bit operands: every row holds the rounded value followed by the rounded
+  // remainder (hi | lo), so each row is twice as long as in double.
+  kp::bf16_t* a1_16 = nullptr;  // N x 2RN
+  kp::bf16_t* c2_16 = nullptr;  // R x N x 2N
+  kp::bf16_t* b3_16 = nullptr;  // RN x 2N
+  kp_precond_info info{};
+};
+
+namespace kp {
+
+// Device memory through the context's allocator.
+int dev_alloc(kp_context* ctx, void** ptr, size_t bytes);
+void dev_free(kp_context* ctx, void* ptr);
+// Grow-only workspace slot.
+int ws_get(kp_context* ctx, int slot, size_t bytes, void** ptr);
+
+// Number of blocks used by the grid-stride reduction kernels.
+constexpr int kRedBlocks = 1024;
+constexpr int kMaxPartials = 65536;
+
+// ---- launchers (each returns a kp_status) ----------------------------------
+int launch_assemble(kp_context* ctx, kp_coeff* c);
+// Sets *bad (device int, zeroed by the caller) when a cell is not finite or <= 0.
+int launch_validate_cells(kp_context* ctx, const double* cells, size_t n, int* bad);
+
+// Stencil q = K p (or out = f - K p when resid), block partials of <p,q> (or ||out||^2).
+int launch_stencil_f64(kp_context* ctx, const double* p, const double* w, const double* f,
+                       double* out, double* partial, int* nparts, const int* done, int N);
+int launch_stencil_f32(kp_context* ctx, const float* p, const float* w, float* out,
+                       double* partial, int* nparts, const int* done, int N);
+int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* w, const double* f,
+                            float* out, double* partial, int* nparts, const int* done, int N);
+
+int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nvals, int mode,
+                    Scalars* s, size_t n3);
+
+// Preconditioner: z = sum_k (C1 x C2 x C3) x for x in the precision's input type.
+int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, double* z,
+                       const int* done);
+// x16 holds s * r rounded to 16 bits, with s = *scale (power of two; NULL means 1);
+// the result z is divided by s again.
+int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, float* z,
+                      const int* done, const double* scale);
+
+// Vector kernels (double vectors: T = double; mixed: T = float).
+int launch_copy_project_f(kp_context* ctx, const double* f, double mean, double* out, size_t n);
+int launch_sum2(kp_context* ctx, const double* a, size_t n, double* partial, int* nparts);
+int launch_cast_f64_f32(kp_context* ctx, const double* a, float* b, size_t n);
+int launch_cast_f32_f64(kp_context* ctx, const float* a, double* b, size_t n);
+int launch_cast_to16(kp_context* ctx, const double* a, bf16_t* b, size_t n, int fp16);
+// b = 16-bit(a * s->x16_scale) (scale 1 when s is NULL); skipped when s->done.
+int launch_cast32_to16(kp_context* ctx, const float* a, bf16_t* b, size_t n, int fp16,
+                       const Scalars* s);
+int launch_fill_f64(kp_context* ctx, double* a, double v, size_t n);
+
+template <typename T>
+int launch_update_xr(kp_context* ctx, double* x, const T* p, T* r, const T* q, bf16_t* r16,
+                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n);
+template <typename T>
+int launch_prec_dots(kp_context* ctx, const T* z, const T* r, const T* q, const Scalars* s,
+                     double* partial, int* nparts, size_t n);
+template <typename T>
+int launch_update_p(kp_context* ctx, const T* z, T* p, const Scalars* s, size_t n);
+int launch_multidot9(kp_context* ctx, const double* const* phi, const double* f, size_t n,
+                     const double* cells, size_t ncells, double* partial, int* nparts);
+
+}  // namespace kp

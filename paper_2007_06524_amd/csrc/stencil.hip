@@ -1,0 +1,232 @@
+// Assembly of the Kronecker-sum stiffness and the 7-point stencil matvec.
+//
+// Stiffness (Section 3.3, eq. As_Kron_d): each unit cell c contributes a_c times
+// the 1D Neumann Laplacian of its n0+1 nodes in one direction and the lumped
+// half-weight identity diag(1/2,1,...,1,1/2) in the two others, wrapped modulo N
+// (the periodization term).  Summed over cells, the weight of the grid edge
+// (p, p+e_l) is the mean of the coefficient over the four voxels that share the
+// edge, and the matrix acts as the 7-point stencil
+//   (K u)(p) = sum_l w_l(p) (u_p - u_{p+e_l}) + w_l(p-e_l) (u_p - u_{p-e_l}).
+// The corrector right-hand sides (eq. FEM_discr_RHS, integrated by parts) are
+// f_l(p) = h (w_l(p) - w_l(p-e_l)) for K = A / h.
+//
+// Both kernels read the C-order [i1][i2][i3] layout with i3 fastest.
+
+#include <cmath>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block of 256 threads: deterministic sum written by thread 0 into *out.
+__device__ __forceinline__ void block_sum_store(double v, double* out) {
+  __shared__ double red[4];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One thread per node; the eight voxels around node p are v = p - 1 + d, d in {0,1}^3.
+__global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ cells, int L, int n0,
+                                                  int N, double h, double* __restrict__ w64,
+                                                  float* __restrict__ w32,
+                                                  double* __restrict__ f) {
+  const size_t n3 = (size_t)N * N * N;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n3) return;
+  const int p3 = (int)(idx % N);
+  const int p2 = (int)((idx / N) % N);
+  const int p1 = (int)(idx / ((size_t)N * N));
+  int c1[2], c2[2], c3[2];
+  c1[0] = ((p1 + N - 1) % N) / n0; c1[1] = p1 / n0;
+  c2[0] = ((p2 + N - 1) % N) / n0; c2[1] = p2 / n0;
+  c3[0] = ((p3 + N - 1) % N) / n0; c3[1] = p3 / n0;
+  double a[2][2][2];
+  for (int d1 = 0; d1 < 2; ++d1)
+    for (int d2 = 0; d2 < 2; ++d2)
+      for (int d3 = 0; d3 < 2; ++d3)
+        a[d1][d2][d3] = cells[((size_t)c1[d1] * L + c2[d2]) * L + c3[d3]];
+  // Edge (p, p+e_l): voxel layer p_l along l, p_t - 1 or p_t across.
+  const double w0 = (((a[1][1][1] + a[1][0][1]) + a[1][1][0]) + a[1][0][0]) / 4.0;
+  const double w0m = (((a[0][1][1] + a[0][0][1]) + a[0][1][0]) + a[0][0][0]) / 4.0;
+  const double w1 = (((a[1][1][1] + a[0][1][1]) + a[1][1][0]) + a[0][1][0]) / 4.0;
+  const double w1m = (((a[1][0][1] + a[0][0][1]) + a[1][0][0]) + a[0][0][0]) / 4.0;
+  const double w2 = (((a[1][1][1] + a[0][1][1]) + a[1][0][1]) + a[0][0][1]) / 4.0;
+  const double w2m = (((a[1][1][0] + a[0][1][0]) + a[1][0][0]) + a[0][0][0]) / 4.0;
+  w64[idx] = w0;
+  w64[n3 + idx] = w1;
+  w64[2 * n3 + idx] = w2;
+  if (w32) {
+    w32[idx] = (float)w0;
+    w32[n3 + idx] = (float)w1;
+    w32[2 * n3 + idx] = (float)w2;
+  }
+  f[idx] = h * (w0 - w0m);
+  f[n3 + idx] = h * (w1 - w1m);
+  f[2 * n3 + idx] = h * (w2 - w2m);
+}
+
+constexpr int kTX = 64;  // i3 extent of a tile (one wavefront)
+constexpr int kTY = 4;   // i2 extent of a tile (four wavefronts)
+
+// 2.5D tiled stencil.  A 64 x 4 block of columns (i2, i3) marches along i1 over
+// TZ planes; the i1 neighbours and w_1(p - e_1) ride in registers, the current
+// plane of u and of w_2, w_3 is staged in LDS for the in-plane neighbours, and
+// neighbours outside the tile (halo, periodic wrap, ragged edges) come from
+// global memory.  MODE 0: out = K u and dot = <u, K u>.  MODE 1: out = f - K u
+// and dot = ||f - K u||^2 (true residual).  Accumulation type C, output type TO.
+template <typename TU, typename TW, typename TO, typename C, int MODE>
+__global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
+                                                 const TW* __restrict__ w,
+                                                 const double* __restrict__ f,
+                                                 TO* __restrict__ out,
+                                                 double* __restrict__ partial,
+                                                 const int* __restrict__ done, int N, int TZ) {
+  if (done && *done) return;
+  __shared__ TU su[kTY][kTX];
+  __shared__ TW sw1[kTY][kTX];
+  __shared__ TW sw2[kTY][kTX];
+  const int tx = threadIdx.x & (kTX - 1);
+  const int ty = threadIdx.x / kTX;
+  const int i3 = blockIdx.x * kTX + tx;
+  const int i2 = blockIdx.y * kTY + ty;
+  const int z0 = blockIdx.z * TZ;
+  const int z1 = min(z0 + TZ, N);
+  const bool act = (i3 < N) && (i2 < N);
+  const size_t NN = (size_t)N * N;
+  const size_t n3 = NN * N;
+  const TW* w0 = w;
+  const TW* w1 = w + n3;
+  const TW* w2 = w + 2 * n3;
+  const int i2m = (i2 == 0) ? N - 1 : i2 - 1;
+  const int i2p = (i2 + 1 >= N) ? 0 : i2 + 1;
+  const int i3m = (i3 == 0) ? N - 1 : i3 - 1;
+  const int i3p = (i3 + 1 >= N) ? 0 : i3 + 1;
+  const size_t col = (size_t)i2 * N + i3;
+  double dot = 0.0;
+  C um = 0, uc = 0, un = 0, w0m = 0;
+  if (act) {
+    const int zm = (z0 == 0) ? N - 1 : z0 - 1;
+    um = (C)u[zm * NN + col];
+    uc = (C)u[z0 * NN + col];
+    w0m = (C)w0[zm * NN + col];
+  }
+  for (int z = z0; z < z1; ++z) {
+    C w0c = 0, w1c = 0, w2c = 0;
+    const size_t base = (size_t)z * NN;
+    if (act) {
+      const int zp = (z + 1 >= N) ? 0 : z + 1;
+      un = (C)u[zp * NN + col];
+      w0c = (C)w0[base + col];
+      w1c = (C)w1[base + col];
+      w2c = (C)w2[base + col];
+      su[ty][tx] = (TU)uc;
+      sw1[ty][tx] = (TW)w1c;
+      sw2[ty][tx] = (TW)w2c;
+    }
+    __syncthreads();
+    if (act) {
+      const C u2m = (ty > 0) ? (C)su[ty - 1][tx] : (C)u[base + (size_t)i2m * N + i3];
+      const C u2p = (ty + 1 < kTY && i2 + 1 < N) ? (C)su[ty + 1][tx] : (C)u[base + (size_t)i2p * N + i3];
+      const C u3m = (tx > 0) ? (C)su[ty][tx - 1] : (C)u[base + (size_t)i2 * N + i3m];
+      const C u3p = (tx + 1 < kTX && i3 + 1 < N) ? (C)su[ty][tx + 1] : (C)u[base + (size_t)i2 * N + i3p];
+      const C w1m = (ty > 0) ? (C)sw1[ty - 1][tx] : (C)w1[base + (size_t)i2m * N + i3];
+      const C w2m = (tx > 0) ? (C)sw2[ty][tx - 1] : (C)w2[base + (size_t)i2 * N + i3m];
+      C ku = w0c * (uc - un) + w0m * (uc - um);
+      ku += w1c * (uc - u2p) + w1m * (uc - u2m);
+      ku += w2c * (uc - u3p) + w2m * (uc - u3m);
+      if (MODE == 0) {
+        const TO o = (TO)ku;
+        out[base + col] = o;
+        dot += (double)uc * (double)o;
+      } else {
+        const double res = f[base + col] - (double)ku;
+        out[base + col] = (TO)res;
+        dot += res * res;
+      }
+    }
+    __syncthreads();
+    um = uc;
+    uc = un;
+    w0m = w0c;
+  }
+  block_sum_store(dot, partial + (blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z)));
+}
+
+template <typename TU, typename TW, typename TO, typename C, int MODE>
+int run_stencil(kp_context* ctx, const TU* u, const TW* w, const double* f, TO* out,
+                double* partial, int* nparts, const int* done, int N) {
+  ScopedTimer tm(ctx, MODE == 1 ? KP_TIMER_RESIDUAL : KP_TIMER_STENCIL);
+  const int gx = (N + kTX - 1) / kTX;
+  const int gy = (N + kTY - 1) / kTY;
+  // Enough planes per block to amortize the register queue, enough blocks to fill 256 CUs.
+  int TZ = 32;
+  while (TZ > 4 && (size_t)gx * gy * ((N + TZ - 1) / TZ) < 2048) TZ /= 2;
+  int gz = (N + TZ - 1) / TZ;
+  while ((size_t)gx * gy * gz > (size_t)kMaxPartials) {
+    TZ *= 2;
+    gz = (N + TZ - 1) / TZ;
+  }
+  hipLaunchKernelGGL((k_stencil<TU, TW, TO, C, MODE>), dim3(gx, gy, gz), dim3(256), 0, ctx->stream,
+                     u, w, f, out, partial, done, N, TZ);
+  KP_HIP(hipGetLastError());
+  *nparts = gx * gy * gz;
+  return KP_OK;
+}
+
+}  // namespace
+
+namespace {
+__global__ __launch_bounds__(256) void k_validate(const double* __restrict__ cells, size_t n,
+                                                  int* __restrict__ bad) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double v = cells[i];
+    if (!(v > 0.0) || !isfinite(v)) atomicOr(bad, 1);
+  }
+}
+}  // namespace
+
+int launch_validate_cells(kp_context* ctx, const double* cells, size_t n, int* bad) {
+  size_t b = (n + 255) / 256;
+  if (b > 1024) b = 1024;
+  hipLaunchKernelGGL(k_validate, dim3((int)b), dim3(256), 0, ctx->stream, cells, n, bad);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_assemble(kp_context* ctx, kp_coeff* c) {
+  ScopedTimer tm(ctx, KP_TIMER_ASSEMBLE);
+  const size_t n3 = (size_t)c->N * c->N * c->N;
+  const int blocks = (int)((n3 + 255) / 256);
+  hipLaunchKernelGGL(k_assemble, dim3(blocks), dim3(256), 0, ctx->stream, c->cells, c->L, c->n0,
+                     c->N, 1.0 / c->N, c->w64, c->w32, c->f);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_stencil_f64(kp_context* ctx, const double* p, const double* w, const double* f,
+                       double* out, double* partial, int* nparts, const int* done, int N) {
+  if (f) return run_stencil<double, double, double, double, 1>(ctx, p, w, f, out, partial, nparts, done, N);
+  return run_stencil<double, double, double, double, 0>(ctx, p, w, nullptr, out, partial, nparts, done, N);
+}
+
+int launch_stencil_f32(kp_context* ctx, const float* p, const float* w, float* out,
+                       double* partial, int* nparts, const int* done, int N) {
+  return run_stencil<float, float, float, float, 0>(ctx, p, w, nullptr, out, partial, nparts, done, N);
+}
+
+int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* w, const double* f,
+                            float* out, double* partial, int* nparts, const int* done, int N) {
+  return run_stencil<double, double, float, double, 1>(ctx, x, w, f, out, partial, nparts, done, N);
+}
+
+}  // namespace kp

@@ -65,6 +65,18 @@ def random_field(N: int, seed, dims: int = 3) -> np.ndarray:
     return g.standard_normal((N,) * dims).astype(np.float64)
 
 
+def even_factors(N: int, R: int, seed, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:
+    """Random positive vectors u with u[i] = u[N - i], shape (3, R, N).
+
+    Test inputs for the Kronecker-product apply (any even symbol gives a real
+    symmetric circulant); the values are uniform on [lo, hi).
+    """
+    g = _rng(seed)
+    half = lo + (hi - lo) * g.random((3, R, N // 2 + 1))
+    idx = np.minimum(np.arange(N), N - np.arange(N))
+    return half[:, :, idx].astype(np.float64)
+
+
 CONFIGS = {
     "c1": dict(L=4, n0=4, law="bernoulli", lo=1.0, hi=10.0, p=0.5, seed=1,
                rank=4, eps=1e-3, tol=1e-8, rhs=(1,), precision="fp64"),
