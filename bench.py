@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true", help="use the size heuristic for GEMM tiles")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain elementwise copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -129,6 +132,15 @@ def main():
     import paper_2007_06524_amd as kp
     from workloads import CONFIGS, config_cells
 
+    if args.copy_probe_mib > 0:
+        # One elementwise kernel that reads and writes exactly copy_probe_mib MiB each:
+        # the reference for scaling the FETCH_SIZE / WRITE_SIZE counters.
+        src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     cfg = CONFIGS["c3"]
     n0, L = cfg["n0"], cfg["L"]
     N = n0 * L
@@ -138,6 +150,9 @@ def main():
     t0 = time.perf_counter()
     pc = kp.Precond(ctx, N, args.eps, args.rank, prec)
     build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tuning = pc.autotune(reps=3) if not args.no_autotune else []
+    tune_s = time.perf_counter() - t0
     co = kp.Coeff(ctx, cells, n0, prec)
     cells_dev = torch.from_numpy(cells).cuda()
 
@@ -193,7 +208,8 @@ def main():
         "config": {"workload": ("checkerboard L=64 n0=4 N=256 (16.8M unknowns), Bernoulli{1,100} p=0.5 "
                                 "seed 3; assembly + 3 corrector solves to 1e-8 + a_hom per step"),
                    "precision": prec, "rank": pc.R, "precond": pc.info,
-                   "precond_build_s": build_s},
+                   "precond_build_s": build_s, "autotune_s": tune_s},
+        "autotune": [{"stage": s, "bm": bm, "bn": bn, "bk": bk, "ms": ms} for s, bm, bn, bk, ms in tuning],
         "iters_per_sec": sum(iters) / elapsed,
         "iters": iters,
         "relres_true": [s["relres_true"] for s in all_stats],
@@ -206,6 +222,8 @@ def main():
     if not args.no_fp64 and prec != "fp64":
         co64 = kp.Coeff(ctx, cells, n0, "fp64")
         pc64 = kp.Precond(ctx, N, args.eps, args.rank, "fp64")
+        if not args.no_autotune:
+            pc64.autotune(reps=2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         phis64, st64 = [], []

@@ -200,6 +200,27 @@ int build_preconditioner(kp_context* ctx, int N, double eps, int rank, int preci
 int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors,
                             int precision, kp_precond** out);
 
+/* Autotuner of the three mode-product GEMMs: times each tile configuration of
+ * each stage on the context stream (`reps` launches after a warm-up, on
+ * scratch operands of the preconditioner's size) and keeps the fastest per
+ * stage for later applies.  table (host, may be NULL) receives up to cap
+ * entries {stage 0..2 (contracting i3, i2, (k,i1)), tile rows, tile columns,
+ * K tile, average ms}; *count the number of configurations timed.
+ * Synchronizes the stream. */
+typedef struct {
+  int stage, bm, bn, bk;
+  double ms;
+} kp_tile_timing;
+int kp_precond_autotune(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* table, int cap,
+                        int* count);
+
+/* Pin (set) or read (get) the tile configuration of the three stages, e.g.
+ * to reuse an earlier tuning: tiles[s] is the position of the configuration
+ * among the ones of stage s in the autotuner's table (0-based), or -1 for the
+ * size heuristic.  set: KP_ERR_ARG for an index out of range. */
+int kp_precond_set_tiles(kp_precond* pc, const int* tiles);
+int kp_precond_get_tiles(const kp_precond* pc, int* tiles);
+
 /* Rank R of a preconditioner (or -1 for NULL). */
 int kp_precond_rank(const kp_precond* pc);
 

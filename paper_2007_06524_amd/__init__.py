@@ -177,6 +177,28 @@ class Precond:
         self.R = lib.kp_precond_rank(h)
         ctx._owned.append(self)
 
+    def autotune(self, reps: int = 5):
+        """Time the tile configurations of the three GEMM stages and keep the fastest.
+
+        Returns [(stage, bm, bn, bk, ms), ...] for every configuration timed."""
+        cap = 64
+        table = (_lib.TileTiming * cap)()
+        n = C.c_int(0)
+        check(load().kp_precond_autotune(self.ctx.handle, self.handle, int(reps), table, cap, C.byref(n)))
+        return [(t.stage, t.bm, t.bn, t.bk, t.ms) for t in table[:min(n.value, cap)]]
+
+    @property
+    def tiles(self):
+        """Tile configuration index per GEMM stage (-1: size heuristic)."""
+        t = (C.c_int * 3)()
+        check(load().kp_precond_get_tiles(self.handle, t))
+        return tuple(t)
+
+    @tiles.setter
+    def tiles(self, value):
+        t = (C.c_int * 3)(*[int(v) for v in value])
+        check(load().kp_precond_set_tiles(self.handle, t))
+
     def apply(self, r):
         """z = sum_k (C1^k x C2^k x C3^k) r, r a float64 CUDA tensor (N, N, N)."""
         import torch

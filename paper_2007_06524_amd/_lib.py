@@ -51,6 +51,10 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TileTiming(C.Structure):
+    _fields_ = [("stage", C.c_int), ("bm", C.c_int), ("bn", C.c_int), ("bk", C.c_int), ("ms", C.c_double)]
+
+
 TIMERS = ("stencil", "gemm_mode3", "gemm_mode2", "gemm_mode1", "vector", "assemble", "residual")
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -78,6 +82,10 @@ SIGNATURES = {
     "kp_precond_from_factors": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                                           C.POINTER(C.c_void_p)]),
     "kp_precond_rank": (C.c_int, [C.c_void_p]),
+    "kp_precond_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(TileTiming), C.c_int,
+                                      C.POINTER(C.c_int)]),
+    "kp_precond_set_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "kp_precond_get_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "kp_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "kp_free_precond": (C.c_int, [C.c_void_p]),
     "pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,

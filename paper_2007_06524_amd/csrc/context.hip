@@ -500,6 +500,33 @@ int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors
 
 int kp_precond_rank(const kp_precond* pc) { return pc ? pc->R : -1; }
 
+int kp_precond_set_tiles(kp_precond* pc, const int* tiles) {
+  if (!pc || !tiles) return fail(KP_ERR_ARG, "kp_precond_set_tiles: NULL argument");
+  const int n = pc->precision == KP_FP64 ? kTiles64 : kTiles16;
+  for (int s = 0; s < 3; ++s)
+    if (tiles[s] < -1 || tiles[s] >= n)
+      return fail(KP_ERR_ARG, "kp_precond_set_tiles: tile index %d of stage %d not in [-1,%d)", tiles[s], s, n);
+  for (int s = 0; s < 3; ++s) pc->tile[s] = tiles[s];
+  return KP_OK;
+}
+
+int kp_precond_get_tiles(const kp_precond* pc, int* tiles) {
+  if (!pc || !tiles) return fail(KP_ERR_ARG, "kp_precond_get_tiles: NULL argument");
+  for (int s = 0; s < 3; ++s) tiles[s] = pc->tile[s];
+  return KP_OK;
+}
+
+int kp_precond_autotune(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* table, int cap,
+                        int* count) {
+  if (!ctx || !pc) return fail(KP_ERR_ARG, "kp_precond_autotune: NULL argument");
+  if (pc->ctx != ctx) return fail(KP_ERR_STATE, "kp_precond_autotune: preconditioner of another context");
+  if (reps < 1 || reps > 1000) return fail(KP_ERR_ARG, "kp_precond_autotune: reps must be 1..1000");
+  KP_HIP(hipSetDevice(ctx->device));
+  KP_TRY(autotune_precond(ctx, pc, reps, table, table ? cap : 0, count));
+  KP_HIP(hipStreamSynchronize(ctx->stream));
+  return KP_OK;
+}
+
 int kp_free_precond(kp_precond* pc) {
   if (!pc) return KP_OK;
   kp_context* ctx = pc->ctx;

@@ -147,6 +147,7 @@ struct kp_precond {
   kp::bf16_t* c2_16 = nullptr;  // R x N x 2N
   kp::bf16_t* b3_16 = nullptr;  // RN x 2N
   kp_precond_info info{};
+  int tile[3] = {-1, -1, -1};   // tile configuration per GEMM stage (-1: size heuristic)
 };
 
 namespace kp {
@@ -160,6 +161,12 @@ int ws_get(kp_context* ctx, int slot, size_t bytes, void** ptr);
 // Number of blocks used by the grid-stride reduction kernels.
 constexpr int kRedBlocks = 1024;
 constexpr int kMaxPartials = 65536;
+// Number of GEMM tile configurations (double and 16-bit kernels).
+constexpr int kTiles64 = 4;
+constexpr int kTiles16 = 8;
+
+int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* table, int cap,
+                     int* count);
 
 // ---- launchers (each returns a kp_status) ----------------------------------
 int launch_assemble(kp_context* ctx, kp_coeff* c);

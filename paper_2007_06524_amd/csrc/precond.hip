@@ -1,24 +1,25 @@
 // Low-Kronecker-rank preconditioner: z = sum_k (C1^k x C2^k x C3^k) x
 // (eq. Lap3DtimesX with the circulants C_l^k = F* diag(u_l^k) F held as dense
-// real symmetric N x N matrices), evaluated as three MFMA GEMMs:
+// real symmetric N x N matrices), evaluated as three MFMA GEMMs, each of the
+// form D = A * B^T with the circulant operand as A and both operands
+// contiguous in the contraction index:
 //
-//   (i)   T[k][j3][i1][i2]   = sum_i3  X[i1][i2][i3]  C3^k[j3][i3]
-//   (ii)  U[(j2,j3)][(k,i1)] = sum_i2  C2^k[j2][i2]   T[k][j3][i1][i2]
+//   (i)   T[k][j3][i1][i2]   = sum_i3     C3^k[j3][i3] X[i1][i2][i3]
+//   (ii)  U[(j2,j3)][(k,i1)] = sum_i2     C2^k[j2][i2] T[k][j3][i1][i2]
 //   (iii) Z[j1][(j2,j3)]     = sum_(k,i1) C1^k[j1][i1] U[(j2,j3)][(k,i1)]
 //
-// Every stage is an "NT" product D = A * Bt^T with both operands contiguous in
-// the contraction index, so each MFMA fragment is one contiguous LDS read.
 // Stage (iii) contracts over R*N at once, which folds the sum over the R
-// Kronecker terms into the GEMM.  The layouts of T and U are chosen by the
-// output address maps of stages (i) and (ii) so that they are the contiguous
-// operands of the next stage.
+// Kronecker terms into the GEMM.  The layouts of T and U are set by the output
+// address maps of stages (i) and (ii) so that each is the contiguous B operand
+// of the next stage.
 //
 // FP64: v_mfma_f64_16x16x4_f64.  BF16 / FP16: v_mfma_f32_16x16x32_{bf16,f16}
-// with float accumulation; intermediates are rounded to the 16-bit type.  In
-// 16 bits every circulant is held as a rounded part plus the rounded remainder
-// and both are contracted (the K extent doubles): the symbol of G_R spans about
-// N^2 / (4 pi^2) * 12 in magnitude across frequencies, more than one 16-bit
-// rounding of the dense circulant entries can resolve.
+// with float accumulation; T and U are rounded to the 16-bit type.  In 16 bits
+// each circulant is held as its rounded value plus the rounded remainder
+// (hi + lo) and both are multiplied into the same accumulator, reusing every
+// fragment of the data operand: the symbol of the low-rank preconditioner
+// spans about 12 N^2 / (4 pi^2) in magnitude across frequencies, more than one
+// 16-bit rounding of the dense circulant entries resolves.
 
 #include <climits>
 
@@ -42,25 +43,22 @@ struct OutMap {
 };
 
 struct GemmArgs {
-  const void* A;   // M x K, row stride lda
+  const void* A;   // M x K, row stride lda (16-bit: remainder plane at +a_lo in each row)
   const void* B;   // Nn x K, row stride ldb  (the transposed right operand)
   void* C;
   int M, Nn, K;
   long long lda, ldb, sAb, sBb;
   OutMap om;
   const int* done;
-  int vec;         // 1: 16-byte operand loads are legal (alignment and K)
-  int krep_a;      // > 0: A is stored with krep_a columns and read at column k mod krep_a
-  int krep_b;      // same for B
+  int vec;                // 1: 16-byte operand loads are legal (alignment and K)
+  long long a_lo;         // > 0: A = A[.., k] + A[.., a_lo + k] (hi + lo planes)
   const double* out_div;  // non-null: results are divided by *out_div
 };
 
 GemmArgs gemm_args(const void* A, const void* B, void* C, long long M, long long Nn, long long K,
                    long long lda, long long ldb, long long sAb, long long sBb, OutMap om,
-                   const int* done, int krep_a = 0, int krep_b = 0,
-                   const double* out_div = nullptr) {
-  return GemmArgs{A, B, C, (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0, krep_a, krep_b,
-                  out_div};
+                   const int* done, long long a_lo = 0, const double* out_div = nullptr) {
+  return GemmArgs{A, B, C, (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0, a_lo, out_div};
 }
 
 __device__ __forceinline__ long long out_addr(const OutMap& o, int m, int n, int b) {
@@ -173,18 +171,22 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 }
 
 // ---------------------------------------------------- BF16 / FP16 MFMA
-// Same structure with K tile 64 (two 16x16x32 MFMA steps); operands are moved
-// as 16-byte vectors of eight 16-bit values; rows are padded by 16 bytes.
-template <int BM, int BN, bool F16, typename TO>
+// 256 threads = 2 x 2 wavefronts, block tile BM x BN, K tile 64 (two
+// 16x16x32 steps).  Operands move as 16-byte vectors of eight 16-bit values;
+// LDS rows are padded by 16 bytes (conflict-free 16-byte fragment reads).
+// With SPLIT the A tile is staged twice (hi and lo planes) and every B
+// fragment feeds two MFMAs.  The next K tile is fetched into registers while
+// the current one is multiplied.
+template <int BM, int BN, int BK, bool F16, bool SPLIT, typename TO>
 __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   if (g.done && *g.done) return;
-  constexpr int BK = 64;
-  constexpr int PAD = 8;
+  constexpr int LDK = BK + 8;
+  constexpr int NP = SPLIT ? 2 : 1;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int VA = BM * BK / 8 / 256, VB = BN * BK / 8 / 256;  // 16-byte vectors per thread
-  __shared__ __attribute__((aligned(16))) bf16_t As[BM][BK + PAD];
-  __shared__ __attribute__((aligned(16))) bf16_t Bs[BN][BK + PAD];
+  __shared__ __attribute__((aligned(16))) bf16_t As[NP][BM][LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t Bs[BN][LDK];
   const int bz = blockIdx.z;
   const bf16_t* __restrict__ A = (const bf16_t*)g.A + (long long)bz * g.sAb;
   const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
@@ -198,23 +200,18 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  u32x4 ra[VA], rb[VB];
-  // 8 consecutive contraction indices of one operand row; with krep > 0 the
-  // operand is repeated along K (column k is read at k mod krep).
-  auto load_vec = [&](const bf16_t* __restrict__ P, long long ld, int rows, int r0, int k0,
-                      int krep, int e, u32x4& dst) {
+  u32x4 ra[NP][VA], rb[VB];
+  auto load_vec = [&](const bf16_t* __restrict__ P, long long ld, int rows, int r0, int k0, int e,
+                      u32x4& dst) {
     const int r = e / (BK / 8), c = (e % (BK / 8)) * 8;
     const int gr = r0 + r, gk = k0 + c;
     if (gr < rows && g.vec && gk + 8 <= g.K) {
-      const int kc = krep ? gk % krep : gk;
-      dst = *(const u32x4*)(P + (long long)gr * ld + kc);
+      dst = *(const u32x4*)(P + (long long)gr * ld + gk);
     } else {
       uint32_t w[4] = {0u, 0u, 0u, 0u};
       if (gr < rows) {
         for (int q = 0; q < 8; ++q) {
-          const int kq = gk + q;
-          const int kc = krep ? kq % krep : kq;
-          const uint32_t v = (kq < g.K) ? (uint32_t)P[(long long)gr * ld + kc] : 0u;
+          const uint32_t v = (gk + q < g.K) ? (uint32_t)P[(long long)gr * ld + gk + q] : 0u;
           w[q >> 1] |= v << (16 * (q & 1));
         }
       }
@@ -223,17 +220,29 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   };
   auto load = [&](int k0) {
 #pragma unroll
-    for (int t = 0; t < VA; ++t) load_vec(A, g.lda, g.M, m0, k0, g.krep_a, tid + 256 * t, ra[t]);
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int t = 0; t < VB; ++t) load_vec(B, g.ldb, g.Nn, n0, k0, g.krep_b, tid + 256 * t, rb[t]);
+      for (int t = 0; t < VA; ++t) load_vec(A + p * g.a_lo, g.lda, g.M, m0, k0, tid + 256 * t, ra[p][t]);
+#pragma unroll
+    for (int t = 0; t < VB; ++t) load_vec(B, g.ldb, g.Nn, n0, k0, tid + 256 * t, rb[t]);
+  };
+  auto mfma = [&](const u32x4& a, const u32x4& b, flt4& c) {
+    if constexpr (F16)
+      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    else
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   };
   load(0);
   for (int k0 = 0; k0 < g.K; k0 += BK) {
 #pragma unroll
-    for (int t = 0; t < VA; ++t) {
-      const int e = tid + 256 * t;
-      *(u32x4*)&As[e / (BK / 8)][(e % (BK / 8)) * 8] = ra[t];
-    }
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int t = 0; t < VA; ++t) {
+        const int e = tid + 256 * t;
+        *(u32x4*)&As[p][e / (BK / 8)][(e % (BK / 8)) * 8] = ra[p][t];
+      }
 #pragma unroll
     for (int t = 0; t < VB; ++t) {
       const int e = tid + 256 * t;
@@ -243,100 +252,128 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
     if (k0 + BK < g.K) load(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 32) {
-      u32x4 af[TM], bfr[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-        af[i] = *(const u32x4*)&As[wm * WM + i * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+      u32x4 bfr[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j)
         bfr[j] = *(const u32x4*)&Bs[wn * WN + j * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int p = 0; p < NP; ++p) {
+        u32x4 af[TM];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          if constexpr (F16)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                __builtin_bit_cast(f16x8, af[i]), __builtin_bit_cast(f16x8, bfr[j]), acc[i][j], 0, 0, 0);
-          else
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, bfr[j]), acc[i][j], 0, 0, 0);
-        }
+        for (int i = 0; i < TM; ++i)
+          af[i] = *(const u32x4*)&As[p][wm * WM + i * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) mfma(af[i], bfr[j], acc[i][j]);
+      }
     }
     __syncthreads();
   }
   const float oscale = g.out_div ? (float)(1.0 / *g.out_div) : 1.0f;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < TN; ++j) {
+    // v_mfma_f32_16x16x32_{bf16,f16} result: item v of lane l is row 4(l/16) + v, column l%16.
+    const int n = n0 + wn * WN + j * 16 + (lane & 15);
+    if (n >= g.Nn) continue;
+    const long long cbase = (long long)(n / g.om.nd) * g.om.sn1 + (long long)(n % g.om.nd) * g.om.sn2 +
+                            (long long)bz * g.om.sb;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      // v_mfma_f32_16x16x32_{bf16,f16} result: item v of lane l is row 4(l/16) + v, column l%16.
-      const int n = n0 + wn * WN + j * 16 + (lane & 15);
-      if (n >= g.Nn) continue;
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + v;
-        if (m < g.M) C[out_addr(g.om, m, n, bz)] = cvt_out<TO, F16>(acc[i][j][v] * oscale);
+        if (m < g.M) C[cbase + (long long)m * g.om.sm] = cvt_out<TO, F16>(acc[i][j][v] * oscale);
       }
-    }
+  }
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-int run_gemm_f64(kp_context* ctx, const GemmArgs& g, int batch) {
-  const bool big = (long long)g.M * g.Nn >= 256LL * 128 * 128;
-  if (big) {
-    dim3 grid((g.Nn + 127) / 128, (g.M + 127) / 128, batch);
-    hipLaunchKernelGGL((k_gemm_f64<128, 128>), grid, dim3(256), 0, ctx->stream, g);
-  } else {
-    dim3 grid((g.Nn + 63) / 64, (g.M + 63) / 64, batch);
-    hipLaunchKernelGGL((k_gemm_f64<64, 64>), grid, dim3(256), 0, ctx->stream, g);
+// Tile configurations (block rows x block columns [x K tile for 16-bit]).  The
+// autotuner times them per stage; without tuning a size heuristic picks one.
+constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
+constexpr int kCfg16[kTiles16][3] = {{64, 64, 64},   {128, 64, 64},  {64, 128, 64},
+                                     {128, 128, 64}, {128, 128, 32}, {256, 128, 64},
+                                     {256, 128, 32}, {128, 256, 32}};
+
+int heuristic64(const GemmArgs& g) {
+  return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
+}
+
+int heuristic16(const GemmArgs& g, int batch) {
+  if (g.M >= 256 && (long long)g.M * g.Nn * batch >= 256LL * 128 * 512) return 5;
+  if (g.M >= 128 && (long long)g.M * g.Nn * batch >= 128LL * 128 * 256) return 3;
+  return 0;
+}
+
+template <int BM, int BN>
+void launch64(kp_context* ctx, const GemmArgs& g, int batch) {
+  dim3 grid((g.Nn + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
+  hipLaunchKernelGGL((k_gemm_f64<BM, BN>), grid, dim3(256), 0, ctx->stream, g);
+}
+
+int run_gemm_f64(kp_context* ctx, const GemmArgs& g, int batch, int cfg) {
+  if (cfg < 0 || cfg >= kTiles64) cfg = heuristic64(g);
+  switch (cfg) {
+    case 0: launch64<64, 64>(ctx, g, batch); break;
+    case 1: launch64<128, 64>(ctx, g, batch); break;
+    case 2: launch64<64, 128>(ctx, g, batch); break;
+    default: launch64<128, 128>(ctx, g, batch); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
+}
+
+template <int BM, int BN, int BK, typename TO>
+void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
+  dim3 grid((g.Nn + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
+  if (g.a_lo) {
+    if (f16) hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, true, true, TO>), grid, dim3(256), 0, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, false, true, TO>), grid, dim3(256), 0, ctx->stream, g);
+  } else {
+    if (f16) hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, true, false, TO>), grid, dim3(256), 0, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, false, false, TO>), grid, dim3(256), 0, ctx->stream, g);
+  }
 }
 
 template <typename TO>
-int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16) {
+int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
   g.vec = (g.K % 8 == 0) && (g.lda % 8 == 0) && (g.ldb % 8 == 0) && (g.sAb % 8 == 0) &&
-          (g.sBb % 8 == 0) && (g.krep_a % 8 == 0) && (g.krep_b % 8 == 0) && aligned16(g.A) &&
-          aligned16(g.B);
-  const bool big = (long long)g.M * g.Nn >= 256LL * 128 * 128;
-  if (big) {
-    dim3 grid((g.Nn + 127) / 128, (g.M + 127) / 128, batch);
-    if (f16) hipLaunchKernelGGL((k_gemm_16<128, 128, true, TO>), grid, dim3(256), 0, ctx->stream, g);
-    else hipLaunchKernelGGL((k_gemm_16<128, 128, false, TO>), grid, dim3(256), 0, ctx->stream, g);
-  } else {
-    dim3 grid((g.Nn + 63) / 64, (g.M + 63) / 64, batch);
-    if (f16) hipLaunchKernelGGL((k_gemm_16<64, 64, true, TO>), grid, dim3(256), 0, ctx->stream, g);
-    else hipLaunchKernelGGL((k_gemm_16<64, 64, false, TO>), grid, dim3(256), 0, ctx->stream, g);
+          (g.sBb % 8 == 0) && (g.a_lo % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+  if (cfg < 0 || cfg >= kTiles16) cfg = heuristic16(g, batch);
+  switch (cfg) {
+    case 0: launch16<64, 64, 64, TO>(ctx, g, batch, f16); break;
+    case 1: launch16<128, 64, 64, TO>(ctx, g, batch, f16); break;
+    case 2: launch16<64, 128, 64, TO>(ctx, g, batch, f16); break;
+    case 3: launch16<128, 128, 64, TO>(ctx, g, batch, f16); break;
+    case 4: launch16<128, 128, 32, TO>(ctx, g, batch, f16); break;
+    case 5: launch16<256, 128, 64, TO>(ctx, g, batch, f16); break;
+    case 6: launch16<256, 128, 32, TO>(ctx, g, batch, f16); break;
+    default: launch16<128, 256, 32, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
 }
 
-// The three stages.  With split = true the circulant operands carry (hi | lo)
-// halves along K, the contraction runs over 2K and the other operand is read
-// twice (k mod K), so that C x = C_hi x + C_lo x is accumulated in float.
+// The three stages.  `planes` = 2 when each circulant row holds (hi | lo).
 struct Stages {
   GemmArgs s1, s2, s3;
 };
 
 Stages make_stages(int N, int R, const void* x, const void* a1, const void* c2, const void* b3,
-                   void* T, void* U, void* z, const int* done, bool split,
-                   const double* out_div) {
+                   void* T, void* U, void* z, const int* done, int planes, const double* out_div) {
   const long long n = N, nn = n * n, n3 = nn * n, RN = (long long)R * N;
-  const long long f = split ? 2 : 1;
-  const int rn = split ? N : 0, rrn = split ? (int)RN : 0;
+  const long long p = planes;
+  const long long lo_n = planes == 2 ? n : 0, lo_rn = planes == 2 ? RN : 0;
   Stages s;
-  // (i) rows (i1,i2), cols (k,j3), K = i3; store transposed: addr = m + n*M.
-  s.s1 = gemm_args(x, b3, T, nn, RN, f * n, n, f * n, 0, 0, OutMap{1, 0, nn, 0, INT_MAX}, done,
-                   rn, 0);
+  // (i) rows (k,j3), cols (i1,i2), K = i3; addr = m*N^2 + n = T[k][j3][i1][i2].
+  s.s1 = gemm_args(b3, x, T, RN, nn, n, p * n, n, 0, 0, OutMap{nn, 0, 1, 0, INT_MAX}, done, lo_n);
   // (ii) batch k: rows j2, cols (j3,i1), K = i2; addr = j2*R*N^2 + j3*R*N + k*N + i1.
-  s.s2 = gemm_args(c2, T, U, n, nn, f * n, f * n, n, f * nn, n3, OutMap{RN * n, RN, 1, n, N}, done,
-                   0, rn);
+  s.s2 = gemm_args(c2, T, U, n, nn, n, p * n, n, p * nn, n3, OutMap{RN * n, RN, 1, n, N}, done, lo_n);
   // (iii) rows j1, cols (j2,j3), K = (k,i1); natural row-major output.
-  s.s3 = gemm_args(a1, U, z, n, nn, f * RN, f * RN, RN, 0, 0, OutMap{nn, 0, 1, 0, INT_MAX}, done,
-                   0, rrn, out_div);
+  s.s3 = gemm_args(a1, U, z, n, nn, RN, p * RN, RN, 0, 0, OutMap{nn, 0, 1, 0, INT_MAX}, done, lo_rn,
+                   out_div);
   return s;
 }
 
@@ -348,18 +385,17 @@ int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, d
   void *T, *U;
   KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(double), &T));
   KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(double), &U));
-  Stages s = make_stages(pc->N, pc->R, x, pc->a1_64, pc->c2_64, pc->b3_64, T, U, z, done, false,
-                         nullptr);
+  Stages s = make_stages(pc->N, pc->R, x, pc->a1_64, pc->c2_64, pc->b3_64, T, U, z, done, 1, nullptr);
   {
     ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE3);
-    KP_TRY(run_gemm_f64(ctx, s.s1, 1));
+    KP_TRY(run_gemm_f64(ctx, s.s1, 1, pc->tile[0]));
   }
   {
     ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE2);
-    KP_TRY(run_gemm_f64(ctx, s.s2, pc->R));
+    KP_TRY(run_gemm_f64(ctx, s.s2, pc->R, pc->tile[1]));
   }
   ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE1);
-  KP_TRY(run_gemm_f64(ctx, s.s3, 1));
+  KP_TRY(run_gemm_f64(ctx, s.s3, 1, pc->tile[2]));
   return KP_OK;
 }
 
@@ -370,18 +406,79 @@ int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, fl
   void *T, *U;
   KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(bf16_t), &T));
   KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(bf16_t), &U));
-  Stages s = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, done, true,
-                         scale);
+  Stages s = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, done, 2, scale);
   {
     ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE3);
-    KP_TRY(run_gemm_16<bf16_t>(ctx, s.s1, 1, f16));
+    KP_TRY(run_gemm_16<bf16_t>(ctx, s.s1, 1, f16, pc->tile[0]));
   }
   {
     ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE2);
-    KP_TRY(run_gemm_16<bf16_t>(ctx, s.s2, pc->R, f16));
+    KP_TRY(run_gemm_16<bf16_t>(ctx, s.s2, pc->R, f16, pc->tile[1]));
   }
   ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE1);
-  KP_TRY(run_gemm_16<float>(ctx, s.s3, 1, f16));
+  KP_TRY(run_gemm_16<float>(ctx, s.s3, 1, f16, pc->tile[2]));
+  return KP_OK;
+}
+
+// Times every tile configuration of every stage (`reps` launches each, after
+// one warm-up launch) on the workspace and keeps the fastest per stage.
+int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* table, int cap,
+                     int* count) {
+  const size_t n3 = (size_t)pc->N * pc->N * pc->N;
+  const bool sixteen = pc->precision != KP_FP64;
+  const size_t el = sixteen ? sizeof(bf16_t) : sizeof(double);
+  void *T, *U, *X, *Z;
+  KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * el, &T));
+  KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * el, &U));
+  KP_TRY(ws_get(ctx, sixteen ? WS_X16 : WS_TMP64, n3 * el, &X));
+  KP_TRY(ws_get(ctx, WS_TMP64B, n3 * sizeof(double), &Z));
+  // Defined operand values (timing does not depend on them).
+  KP_HIP(hipMemsetAsync(T, 0, n3 * pc->R * el, ctx->stream));
+  KP_HIP(hipMemsetAsync(U, 0, n3 * pc->R * el, ctx->stream));
+  KP_HIP(hipMemsetAsync(X, 0, n3 * el, ctx->stream));
+  Stages s = sixteen ? make_stages(pc->N, pc->R, X, pc->a1_16, pc->c2_16, pc->b3_16, T, U, Z, nullptr, 2,
+                                   nullptr)
+                     : make_stages(pc->N, pc->R, X, pc->a1_64, pc->c2_64, pc->b3_64, T, U, Z, nullptr, 1,
+                                   nullptr);
+  const bool f16 = pc->precision == KP_MIXED_FP16;
+  const int ncfg = sixteen ? kTiles16 : kTiles64;
+  int n = 0;
+  for (int st = 0; st < 3; ++st) {
+    const GemmArgs& g = st == 0 ? s.s1 : (st == 1 ? s.s2 : s.s3);
+    const int batch = st == 1 ? pc->R : 1;
+    double best = 1e300;
+    int best_cfg = -1;
+    for (int c = 0; c < ncfg; ++c) {
+      auto run = [&]() -> int {
+        if (!sixteen) return run_gemm_f64(ctx, g, batch, c);
+        if (st == 2) return run_gemm_16<float>(ctx, g, batch, f16, c);
+        return run_gemm_16<bf16_t>(ctx, g, batch, f16, c);
+      };
+      KP_TRY(run());
+      KP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+      for (int r = 0; r < reps; ++r) KP_TRY(run());
+      KP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+      KP_HIP(hipEventSynchronize(ctx->ev1));
+      float ms = 0.f;
+      KP_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      const double avg = (double)ms / reps;
+      if (table && n < cap) {
+        kp_tile_timing& e = table[n];
+        e.stage = st;
+        e.bm = sixteen ? kCfg16[c][0] : kCfg64[c][0];
+        e.bn = sixteen ? kCfg16[c][1] : kCfg64[c][1];
+        e.bk = sixteen ? kCfg16[c][2] : 16;
+        e.ms = avg;
+      }
+      ++n;
+      if (avg < best) {
+        best = avg;
+        best_cfg = c;
+      }
+    }
+    pc->tile[st] = best_cfg;
+  }
+  if (count) *count = n;
   return KP_OK;
 }
 

@@ -291,3 +291,25 @@ def test_coeff_update_and_timing(ctx):
     w2, _ = co.fields()
     assert torch.equal(w, w2)          # fields unchanged after a rejected update
     co.free()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed_bf16", 1e-2), ("mixed_fp16", 2e-3)])
+def test_every_tile_configuration_matches(ctx, prec, tol):
+    """The autotuner's candidates all compute the same operator: tune, then check the
+    apply with the chosen tiles, on a ragged size (N = 72, R = 3)."""
+    F = even_factors(72, 3, seed=72)
+    pc = kp.Precond(ctx, 72, precision=prec, factors=F)
+    ncfg = 4 if prec == "fp64" else 8
+    table = pc.autotune(reps=1)
+    assert len(table) == 3 * ncfg and all(t[4] > 0 for t in table)
+    tuned = pc.tiles
+    assert all(0 <= t < ncfg for t in tuned)
+    x = random_field(72, seed=8)
+    ref = lr.kron_apply(F, x)
+    for c in range(ncfg):
+        pc.tiles = (c, c, c)
+        z = host(pc.apply(dev(x)))
+        assert np.linalg.norm(z - ref) / np.linalg.norm(ref) <= tol, c
+    with pytest.raises(kp.KronPCGError):
+        pc.tiles = (ncfg, 0, 0)
+    pc.free()
