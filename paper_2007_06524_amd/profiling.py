@@ -1,0 +1,154 @@
+"""Summaries of rocprofv3 output for the solver's kernels.
+
+    python -m paper_2007_06524_amd.profiling --trace DIR [--fetch DIR] [--write DIR]
+        [--copy-mib M] [--out FILE] [--title TEXT] [--command TEXT ...]
+
+DIR is a rocprofv3 output directory (CSV files from --output-format csv, or
+the rocpd SQLite database).  The summary is a Markdown table per kernel:
+launches, average duration, and, when counter runs are given, the average
+FETCH_SIZE / WRITE_SIZE per launch.  Counter values are scaled by the ratio
+of the known traffic of the calibration copy kernel (an elementwise kernel
+that reads and writes M MiB, launched first by bench.py --copy-probe-mib M)
+to what the same counter reports for it.
+"""
+
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import os
+import sqlite3
+
+
+def _csv_rows(directory, suffix):
+    files = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _col(row, *names):
+    low = {k.lower(): k for k in row}
+    for n in names:
+        if n.lower() in low:
+            return row[low[n.lower()]]
+    raise KeyError(names)
+
+
+def kernel_durations(directory):
+    """{kernel name: [durations in ns]}"""
+    out = collections.defaultdict(list)
+    rows = _csv_rows(directory, "kernel_trace.csv")
+    if rows:
+        for r in rows:
+            name = _col(r, "Kernel_Name", "kernel_name")
+            t0 = int(_col(r, "Start_Timestamp", "start"))
+            t1 = int(_col(r, "End_Timestamp", "end"))
+            out[name].append(t1 - t0)
+        return out
+    for db in glob.glob(os.path.join(directory, "**", "*.db"), recursive=True):
+        con = sqlite3.connect(db)
+        for name, t0, t1 in con.execute("select name, start, end from kernels"):
+            out[name].append(int(t1) - int(t0))
+    return out
+
+
+def kernel_counters(directory, counter):
+    """{kernel name: [counter value per dispatch]}"""
+    out = collections.defaultdict(list)
+    rows = _csv_rows(directory, "counter_collection.csv")
+    if rows:
+        for r in rows:
+            if _col(r, "Counter_Name", "counter_name") != counter:
+                continue
+            out[_col(r, "Kernel_Name", "kernel_name")].append(float(_col(r, "Counter_Value", "value")))
+        return out
+    for db in glob.glob(os.path.join(directory, "**", "*.db"), recursive=True):
+        con = sqlite3.connect(db)
+        for name, val in con.execute(
+                "select kernel_name, value from counters_collection where counter_name = ?", (counter,)):
+            out[name].append(float(val))
+    return out
+
+
+def _short(name, width=72):
+    name = name.replace("kp::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
+def _calibration(counts, copy_mib):
+    """Scale factor: known KiB of the copy kernel / reported KiB."""
+    if not copy_mib:
+        return None
+    cand = [k for k in counts if "elementwise" in k and counts[k]]
+    if not cand:
+        return None
+    known = copy_mib * 1024.0
+    best = max(cand, key=lambda k: max(counts[k]))
+    reported = max(counts[best])
+    return known / reported if reported > 0 else None
+
+
+def summarize(trace, fetch=None, write=None, copy_mib=0, title="", commands=()):
+    dur = kernel_durations(trace)
+    fc = kernel_counters(fetch, "FETCH_SIZE") if fetch else {}
+    wc = kernel_counters(write, "WRITE_SIZE") if write else {}
+    ff = _calibration(fc, copy_mib)
+    wf = _calibration(wc, copy_mib)
+    total = sum(sum(v) for v in dur.values())
+    lines = []
+    if title:
+        lines += [f"# {title}", ""]
+    if commands:
+        lines += ["Commands (run from the repository root on the GPU box):", "", "```"]
+        lines += list(commands)
+        lines += ["```", ""]
+    if fetch or write:
+        lines += [f"Counter calibration (copy kernel of {copy_mib} MiB read + {copy_mib} MiB written): "
+                  f"FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {wf:.3f}" if ff and wf else
+                  "Counter calibration: not available", ""]
+    hdr = "| kernel | launches | avg us | total ms | % |"
+    sep = "|---|---:|---:|---:|---:|"
+    if fetch or write:
+        hdr += " fetch MB/launch | write MB/launch |"
+        sep += "---:|---:|"
+    lines += [hdr, sep]
+    for name, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        row = (f"| `{_short(name)}` | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {sum(v) / 1e6:.3f} | "
+               f"{100.0 * sum(v) / total:.1f} |")
+        if fetch or write:
+            def mb(counts, fac):
+                vals = counts.get(name)
+                if not vals:
+                    return "-"
+                avg = sum(vals) / len(vals) * (fac or 1.0)
+                return f"{avg * 1024 / 1e6:.1f}"
+            row += f" {mb(fc, ff)} | {mb(wc, wf)} |"
+        lines.append(row)
+    return "\n".join(lines) + "\n"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--title", default="")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--out")
+    a = ap.parse_args(argv)
+    text = summarize(a.trace, a.fetch, a.write, a.copy_mib, a.title, a.command)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(text)
+    else:
+        print(text)
+
+
+if __name__ == "__main__":
+    main()
