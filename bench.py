@@ -37,7 +37,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="mixed_bf16", choices=["mixed_bf16", "mixed_fp16", "fp64"])
-    ap.add_argument("--rank", type=int, default=0, help="canonical rank (0: from eps)")
+    # R = 5 minimized the measured time to tolerance on this workload among
+    # R = 5, 6, 8 (eps rule): fewer MFMA flops per apply outweigh the extra
+    # iterations of the wider rho spread (1.26 at R = 5, 1.02 at R = 8).
+    ap.add_argument("--rank", type=int, default=5, help="canonical rank (0: from eps)")
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

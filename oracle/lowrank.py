@@ -21,6 +21,9 @@ builder independently):
     t_k = e^{s_k}, w_k = eta*t_k.  (eta, shift) are taken from a fixed grid,
     minimizing the largest relative error on 257 geometric samples of
     [a, b] = [mu_1, 12].  (The paper's 1/pi prefactor is read as a typo.)
+    The nodes and weights are then refined towards the best relative
+    approximation of 1/x on [a, b] by R exponentials (refined_quadrature);
+    "the quadrature" below means the refined one.
  3. The zero mode of G+ is annihilated by the zero-mean projection applied to
     every preconditioned vector, so its value is free; it is set to the
     quadrature's value q(0) = sum_k w_k so that the tensor is smooth there.
@@ -69,6 +72,71 @@ def laplace_quadrature(R: int, a: float, b: float):
             err = np.max(np.abs(x * q - 1.0))
             if best is None or err < best[0]:
                 best = (err, t, w)
+    return best[1], best[2], best[0]
+
+
+REFINE_SAMPLES = 513
+REFINE_OUTER = 20
+REFINE_INNER = 50
+
+
+def refined_quadrature(R: int, a: float, b: float):
+    """The quadrature of laplace_quadrature, refined towards the best relative
+    (minimax) approximation of 1/x on [a, b] by R exponentials.
+
+    Parameters theta = (ln t_k, ln w_k).  Outer loop (Lawson): weights on 513
+    geometric samples, multiplied by sqrt(|e|/max|e| + 1e-3) after each pass
+    (e = x q(x) - 1).  Inner loop: damped Gauss-Newton on the weighted
+    residual, (J^T J + lam D) d = -J^T r with D = diag(J^T J) + 1e-12 max
+    diag(J^T J) and each component of d clipped to [-2, 2]; a step is kept
+    only if it lowers the weighted sum of
+    squares (then lam /= 10, floor 1e-12), else lam *= 10 (at most 10 tries).
+    The iterate with the smallest max |e| is returned.
+    """
+    t, w, err0 = laplace_quadrature(R, a, b)
+    x = a * (b / a) ** (np.arange(REFINE_SAMPLES) / (REFINE_SAMPLES - 1))
+    th = np.concatenate([np.log(t), np.log(w)])
+
+    def resid(th, wts):
+        tt, ww = np.exp(th[:R]), np.exp(th[R:])
+        E = np.exp(-np.outer(x, tt)) * ww[None, :]          # (M, R): w_k exp(-t_k x)
+        e = x * E.sum(axis=1) - 1.0
+        return e, E, tt
+
+    best = (err0, t, w)
+    wts = np.ones_like(x)
+    for _ in range(REFINE_OUTER):
+        lam = 1e-3
+        for _ in range(REFINE_INNER):
+            e, E, tt = resid(th, wts)
+            r = wts * e
+            J = np.concatenate([(wts * x)[:, None] * (-x[:, None] * tt[None, :] * E),
+                                (wts * x)[:, None] * E], axis=1)
+            A = J.T @ J
+            g = J.T @ r
+            D = np.diag(A) + 1e-12 * np.diag(A).max()
+            f0 = float(r @ r)
+            accepted = False
+            for _ in range(10):
+                d = np.linalg.solve(A + lam * np.diag(D), -g)
+                d = np.clip(d, -2.0, 2.0)
+                e1, _, _ = resid(th + d, wts)
+                r1 = wts * e1
+                f1 = float(r1 @ r1)
+                if np.isfinite(f1) and f1 < f0:
+                    th = th + d
+                    lam = max(lam / 10.0, 1e-12)
+                    accepted = True
+                    break
+                lam *= 10.0
+            if not accepted or f0 - f1 <= 1e-15 * f0:
+                break
+        e, _, _ = resid(th, np.ones_like(x))
+        m = float(np.abs(e).max())
+        if m < best[0]:
+            best = (m, np.exp(th[:R]), np.exp(th[R:]))
+        wts = wts * np.sqrt(np.abs(e) / m + 1e-3)
+        wts = wts / wts.max()
     return best[1], best[2], best[0]
 
 
@@ -160,7 +228,7 @@ def canonical_preconditioner(N: int, eps: float = 1e-3, rank: int = 0):
     S = s[:, None, None] * s[None, :, None] * s[None, None, :]
 
     R_ref = rank if rank > 0 else 12
-    t, w, _ = laplace_quadrature(R_ref, a, b)
+    t, w, _ = refined_quadrature(R_ref, a, b)
     Gt = pinv_symbol(N)
     Gt[0, 0, 0] = w.sum()
     W = S * Gt
@@ -171,7 +239,7 @@ def canonical_preconditioner(N: int, eps: float = 1e-3, rank: int = 0):
 
     ranks = [rank] if rank > 0 else list(range(2, rT + 1))
     for R in ranks:
-        t, w, qerr = laplace_quadrature(R, a, b)
+        t, w, qerr = refined_quadrature(R, a, b)
         uq = quadrature_factors(mu, t, w)                  # (R, N)
         V0 = U.T @ (s[:, None] * uq.T)                     # (rT, R)
         V = cp_als(B, V0)

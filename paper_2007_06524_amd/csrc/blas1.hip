@@ -140,6 +140,38 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   }
 }
 
+// Four consecutive elements per thread and step, moved as one 16-byte (float)
+// or two 16-byte (double) accesses; the n % 4 tail is handled element-wise.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float4 type;
+};
+template <>
+struct Vec4<double> {
+  typedef double4 type;
+};
+
+template <typename T>
+__device__ __forceinline__ void ld4(const T* __restrict__ p, size_t i, T (&v)[4]) {
+  const typename Vec4<T>::type t = *(const typename Vec4<T>::type*)(p + i);
+  v[0] = t.x;
+  v[1] = t.y;
+  v[2] = t.z;
+  v[3] = t.w;
+}
+
+template <typename T>
+__device__ __forceinline__ void st4(T* __restrict__ p, size_t i, const T (&v)[4]) {
+  typename Vec4<T>::type t;
+  t.x = v[0];
+  t.y = v[1];
+  t.z = v[2];
+  t.w = v[3];
+  *(typename Vec4<T>::type*)(p + i) = t;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, const T* __restrict__ p,
                                                    T* __restrict__ r, const T* __restrict__ q,
@@ -151,7 +183,33 @@ __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, const
   const T ta = (T)alpha;
   const float sc = (float)s->x16_scale;
   double acc[1] = {0.0};
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+  const size_t stride = (size_t)gridDim.x * 256, n4 = n / 4;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n4; c += stride) {
+    const size_t i = 4 * c;
+    T pv[4], rv[4], qv[4];
+    double xv[4];
+    ld4(p, i, pv);
+    ld4(r, i, rv);
+    ld4(q, i, qv);
+    ld4(x, i, xv);
+    ushort4 h;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xv[e] += alpha * (double)pv[e];
+      rv[e] = rv[e] - ta * qv[e];
+      acc[0] += (double)rv[e] * (double)rv[e];
+    }
+    st4(x, i, xv);
+    st4(r, i, rv);
+    if (r16) {
+      h.x = to16((float)rv[0] * sc, fp16);
+      h.y = to16((float)rv[1] * sc, fp16);
+      h.z = to16((float)rv[2] * sc, fp16);
+      h.w = to16((float)rv[3] * sc, fp16);
+      *(ushort4*)(r16 + i) = h;
+    }
+  }
+  for (size_t i = 4 * n4 + (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const T pi = p[i];
     x[i] += alpha * (double)pi;
     const T rn = r[i] - ta * q[i];
@@ -170,34 +228,54 @@ __global__ __launch_bounds__(256) void k_prec_dots(const T* __restrict__ z, cons
                                                    double* __restrict__ partial, size_t n) {
   if (s->done) return;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const double zi = (double)z[i], ri = (double)r[i];
-    acc[0] += ri * zi;
-    acc[2] += zi;
-    acc[3] += ri;
-    if (q) {
-      const double qi = (double)q[i];
+  const size_t stride = (size_t)gridDim.x * 256, n4 = n / 4;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n4; c += stride) {
+    const size_t i = 4 * c;
+    T zv[4], rv[4], qv[4] = {0, 0, 0, 0};
+    ld4(z, i, zv);
+    ld4(r, i, rv);
+    if (q) ld4(q, i, qv);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double zi = (double)zv[e], ri = (double)rv[e], qi = (double)qv[e];
+      acc[0] += ri * zi;
       acc[1] += qi * zi;
+      acc[2] += zi;
+      acc[3] += ri;
       acc[4] += qi;
     }
+  }
+  for (size_t i = 4 * n4 + (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const double zi = (double)z[i], ri = (double)r[i], qi = q ? (double)q[i] : 0.0;
+    acc[0] += ri * zi;
+    acc[1] += qi * zi;
+    acc[2] += zi;
+    acc[3] += ri;
+    acc[4] += qi;
   }
   block_sums_store<5>(acc, partial + blockIdx.x, gridDim.x);
 }
 
-// p = (z - mean(z)) + beta p
+// p = (z - mean(z)) + beta p  (beta = 0: restart, p may hold stale or uninitialized values)
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_p(const T* __restrict__ z, T* __restrict__ p,
                                                   const Scalars* __restrict__ s, size_t n) {
   if (s->done) return;
   const T beta = (T)s->beta;
   const T mz = (T)s->mz;
-  if (s->beta == 0.0) {  // restart: p may hold stale or uninitialized values
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-      p[i] = z[i] - mz;
-    return;
+  const bool restart = s->beta == 0.0;
+  const size_t stride = (size_t)gridDim.x * 256, n4 = n / 4;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n4; c += stride) {
+    const size_t i = 4 * c;
+    T zv[4], pv[4] = {0, 0, 0, 0};
+    ld4(z, i, zv);
+    if (!restart) ld4(p, i, pv);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pv[e] = restart ? zv[e] - mz : (zv[e] - mz) + beta * pv[e];
+    st4(p, i, pv);
   }
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-    p[i] = (z[i] - mz) + beta * p[i];
+  for (size_t i = 4 * n4 + (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    p[i] = restart ? z[i] - mz : (z[i] - mz) + beta * p[i];
 }
 
 __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ a, size_t n,

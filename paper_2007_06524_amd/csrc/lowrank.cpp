@@ -11,7 +11,9 @@
 //     1/x ~ sum_k w_k exp(-t_k x), t_k = e^{s_k}, w_k = eta t_k.  (eta, shift)
 //     come from the grid eta = 0.30 + 0.025 j (j < 49), shift = -2 + 0.1 i
 //     (i < 61), minimizing max |x q(x) - 1| on 257 geometric samples of
-//     [mu_1, 12] (the first strict minimum in that scan order).
+//     [mu_1, 12] (the first strict minimum in that scan order), then refined
+//     towards the best relative approximation of 1/x by R exponentials
+//     (refined_quadrature below).
 //  3. The zero mode is removed by the zero-mean projection of the solver, so
 //     its value is free: it is set to the quadrature value sum_k w_k (rank 12,
 //     or the requested rank) to keep the tensor smooth.
@@ -84,6 +86,112 @@ Quadrature laplace_quadrature(int R, double a, double b) {
         have = true;
       }
     }
+  }
+  return best;
+}
+
+// Solve G x = b for an R x R system (partial pivoting); G and b are copied.
+void solve_small(std::vector<double> G, std::vector<double>& b, int R);
+
+// The quadrature refined towards the best relative (minimax) approximation of
+// 1/x on [a, b] by R exponentials: parameters (ln t_k, ln w_k); Lawson
+// reweighting (20 passes) of damped Gauss-Newton steps (at most 50 per pass,
+// 10 damping tries per step, steps clipped to [-2, 2] per component) on 513
+// geometric samples; the iterate with the smallest max relative error wins.
+Quadrature refined_quadrature(int R, double a, double b) {
+  Quadrature best = laplace_quadrature(R, a, b);
+  constexpr int M = 513;
+  std::vector<double> x(M), wts(M, 1.0);
+  for (int m = 0; m < M; ++m) x[m] = a * std::pow(b / a, (double)m / (double)(M - 1));
+  const int P = 2 * R;
+  std::vector<double> th(P), E((size_t)M * R), e(M), tt(R);
+  for (int k = 0; k < R; ++k) {
+    th[k] = std::log(best.t[k]);
+    th[R + k] = std::log(best.w[k]);
+  }
+  // e = x q(x) - 1 at parameters p; also E[m][k] = w_k exp(-t_k x_m) and tt = t.
+  auto resid = [&](const std::vector<double>& p, std::vector<double>& ee) {
+    for (int k = 0; k < R; ++k) tt[k] = std::exp(p[k]);
+    for (int m = 0; m < M; ++m) {
+      double q = 0.0;
+      for (int k = 0; k < R; ++k) {
+        const double v = std::exp(-x[m] * tt[k]) * std::exp(p[R + k]);
+        E[(size_t)m * R + k] = v;
+        q += v;
+      }
+      ee[m] = x[m] * q - 1.0;
+    }
+  };
+  auto wsum2 = [&](const std::vector<double>& ee) {
+    double f = 0.0;
+    for (int m = 0; m < M; ++m) f += (wts[m] * ee[m]) * (wts[m] * ee[m]);
+    return f;
+  };
+  std::vector<double> J((size_t)M * P), A((size_t)P * P), g(P), D(P), d(P), th1(P), e1(M);
+  for (int outer = 0; outer < 20; ++outer) {
+    double lam = 1e-3;
+    for (int inner = 0; inner < 50; ++inner) {
+      resid(th, e);
+      for (int m = 0; m < M; ++m) {
+        const double s = wts[m] * x[m];
+        for (int k = 0; k < R; ++k) {
+          const double v = E[(size_t)m * R + k];
+          J[(size_t)m * P + k] = s * (-x[m] * tt[k] * v);
+          J[(size_t)m * P + R + k] = s * v;
+        }
+      }
+      double dmax = 0.0;
+      for (int i = 0; i < P; ++i) {
+        for (int j = 0; j < P; ++j) {
+          double acc = 0.0;
+          for (int m = 0; m < M; ++m) acc += J[(size_t)m * P + i] * J[(size_t)m * P + j];
+          A[(size_t)i * P + j] = acc;
+        }
+        double acc = 0.0;
+        for (int m = 0; m < M; ++m) acc += J[(size_t)m * P + i] * (wts[m] * e[m]);
+        g[i] = acc;
+        dmax = std::max(dmax, A[(size_t)i * P + i]);
+      }
+      for (int i = 0; i < P; ++i) D[i] = A[(size_t)i * P + i] + 1e-12 * dmax;
+      const double f0 = wsum2(e);
+      double f1 = f0;
+      bool accepted = false;
+      for (int tries = 0; tries < 10; ++tries) {
+        std::vector<double> Gm(A);
+        for (int i = 0; i < P; ++i) {
+          Gm[(size_t)i * P + i] += lam * D[i];
+          d[i] = -g[i];
+        }
+        solve_small(Gm, d, P);
+        for (int i = 0; i < P; ++i) th1[i] = th[i] + std::min(2.0, std::max(-2.0, d[i]));
+        resid(th1, e1);
+        f1 = wsum2(e1);
+        if (std::isfinite(f1) && f1 < f0) {
+          th = th1;
+          lam = std::max(lam / 10.0, 1e-12);
+          accepted = true;
+          break;
+        }
+        lam *= 10.0;
+      }
+      if (!accepted || f0 - f1 <= 1e-15 * f0) break;
+    }
+    resid(th, e);
+    double mx = 0.0;
+    for (int m = 0; m < M; ++m) mx = std::max(mx, std::fabs(e[m]));
+    if (mx < best.err) {
+      best.err = mx;
+      for (int k = 0; k < R; ++k) {
+        best.t[k] = std::exp(th[k]);
+        best.w[k] = std::exp(th[R + k]);
+      }
+    }
+    double wmax = 0.0;
+    for (int m = 0; m < M; ++m) {
+      wts[m] *= std::sqrt(std::fabs(e[m]) / mx + 1e-3);
+      wmax = std::max(wmax, wts[m]);
+    }
+    for (int m = 0; m < M; ++m) wts[m] /= wmax;
   }
   return best;
 }
@@ -246,7 +354,7 @@ extern "C" int kp_lowrank_factors(int N, double eps, int rank, double* out, size
   for (int i = 0; i < nr; ++i) s[i] = std::cbrt(mu[i] + mu[1]);
 
   // 1-4: weighted symbol on the reduced grid.
-  const Quadrature qref = laplace_quadrature(rank > 0 ? rank : 12, a, b);
+  const Quadrature qref = refined_quadrature(rank > 0 ? rank : 12, a, b);
   double fill = 0.0;
   for (double w : qref.w) fill += w;
   const size_t nr2 = (size_t)nr * nr, nr3 = nr2 * nr;
@@ -349,7 +457,7 @@ extern "C" int kp_lowrank_factors(int N, double eps, int rank, double* out, size
   std::vector<double> uq;
   for (int Rc : ranks) {
     R = Rc;
-    q = laplace_quadrature(R, a, b);
+    q = refined_quadrature(R, a, b);
     uq.assign((size_t)R * nr, 0.0);  // [k][i] reduced
     for (int k = 0; k < R; ++k)
       for (int i = 0; i < nr; ++i) uq[(size_t)k * nr + i] = std::cbrt(q.w[k]) * std::exp(-q.t[k] * mu[i]);

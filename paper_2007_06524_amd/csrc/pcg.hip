@@ -224,14 +224,28 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   int queued = 0;
   int status = KP_NOT_CONVERGED;
   double rr_true = 0.0;
+  // Chunk length: at most `chunk`, shortened to the number of iterations the
+  // recent convergence rate predicts are left, so that few launches are queued
+  // after convergence (they would see the flag and return at once).
+  int prev_it = -1;
+  double prev_rr = 0.0;
+  int predicted = chunk;
   while (true) {
-    const int todo = std::min(chunk, o.maxit - queued);
+    const int todo = std::min(std::min(chunk, predicted), o.maxit - queued);
     for (int i = 0; i < todo; ++i) {
       const bool replace = o.replace_every > 0 && ((queued + 1) % o.replace_every) == 0;
       KP_TRY(iteration(S, replace));
       ++queued;
     }
     KP_TRY(read_scalars(S, &h));
+    predicted = chunk;
+    if (prev_it >= 0 && h.iters > prev_it && h.rr > 0.0 && prev_rr > h.rr && h.rr > h.tol2ff) {
+      const double rate = std::log(h.rr / prev_rr) / (double)(h.iters - prev_it);  // < 0
+      const double left = std::log(h.tol2ff / h.rr) / rate;
+      if (std::isfinite(left)) predicted = std::max(1, (int)std::ceil(left));
+    }
+    prev_it = h.iters;
+    prev_rr = h.rr;
     if (h.breakdown) {
       st.iters = h.iters;
       if (stats) *stats = st;

@@ -66,6 +66,16 @@ __device__ __forceinline__ long long out_addr(const OutMap& o, int m, int n, int
          (long long)b * o.sb;
 }
 
+// Block-to-tile map over a 1D grid of Mt x Nt tiles (z = batch), column tile
+// fastest: concurrently resident blocks sweep along the data operand, and the
+// (small) circulant operand stays in every L2.  (An XCD-grouped order that
+// keeps the row tiles of one column tile together measured slower.)
+__device__ __forceinline__ void tile_of(int Mt, int& mt, int& nt) {
+  const int Nt = gridDim.x / Mt;
+  nt = blockIdx.x % Nt;
+  mt = blockIdx.x / Nt;
+}
+
 __device__ __forceinline__ bf16_t f32_to_bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
   if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
@@ -102,7 +112,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   const double* __restrict__ A = (const double*)g.A + (long long)bz * g.sAb;
   const double* __restrict__ B = (const double*)g.B + (long long)bz * g.sBb;
   double* __restrict__ C = (double*)g.C;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  int mt, nt;
+  tile_of((g.M + BM - 1) / BM, mt, nt);
+  const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   dbl4 acc[TM][TN];
@@ -191,7 +203,9 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   const bf16_t* __restrict__ A = (const bf16_t*)g.A + (long long)bz * g.sAb;
   const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
   TO* __restrict__ C = (TO*)g.C;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  int mt, nt;
+  tile_of((g.M + BM - 1) / BM, mt, nt);
+  const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   flt4 acc[TM][TN];
@@ -309,7 +323,7 @@ int heuristic16(const GemmArgs& g, int batch) {
 
 template <int BM, int BN>
 void launch64(kp_context* ctx, const GemmArgs& g, int batch) {
-  dim3 grid((g.Nn + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
+  dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
   hipLaunchKernelGGL((k_gemm_f64<BM, BN>), grid, dim3(256), 0, ctx->stream, g);
 }
 
@@ -327,7 +341,7 @@ int run_gemm_f64(kp_context* ctx, const GemmArgs& g, int batch, int cfg) {
 
 template <int BM, int BN, int BK, typename TO>
 void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
-  dim3 grid((g.Nn + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
+  dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
   if (g.a_lo) {
     if (f16) hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, true, true, TO>), grid, dim3(256), 0, ctx->stream, g);
     else hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, false, true, TO>), grid, dim3(256), 0, ctx->stream, g);

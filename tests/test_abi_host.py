@@ -40,10 +40,13 @@ def test_lowrank_factors_match_oracle(N, eps, rank):
     assert info["rank"] == io["R"] and info["tucker_rank"] == io["rT"]
     assert info["source"] == (0 if io["source"] == "als" else 1)
     GR, GRo = lr.symbol_from_factors(F), lr.symbol_from_factors(Fo)
-    assert np.abs(GR - GRo).max() <= 1e-10 * np.abs(GRo).max()
-    assert abs(info["rho_min"] - io["rho_min"]) < 1e-10
-    assert abs(info["rho_max"] - io["rho_max"]) < 1e-10
-    assert abs(info["cancellation"] - io["cancellation"]) < 1e-8 * io["cancellation"]
+    # The quadrature refinement is iterative (different linear solvers on the
+    # two sides), so the two constructions agree to the refinement's accuracy.
+    assert np.abs(GR - GRo).max() <= 1e-6 * np.abs(GRo).max()
+    assert abs(info["rho_min"] - io["rho_min"]) < 1e-7
+    assert abs(info["rho_max"] - io["rho_max"]) < 1e-7
+    assert abs(info["quad_rel_err"] - io["quad_rel_err"]) < 1e-6 * io["quad_rel_err"]
+    assert abs(info["cancellation"] - io["cancellation"]) < 1e-6 * io["cancellation"]
     np.testing.assert_allclose(F, F[:, :, (-np.arange(N)) % N], atol=0)   # even factors
     lo, hi = lr.rho_range(F)
     assert abs(lo - info["rho_min"]) < 1e-12 and abs(hi - info["rho_max"]) < 1e-12
