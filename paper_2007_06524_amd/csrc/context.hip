@@ -502,7 +502,7 @@ int kp_precond_rank(const kp_precond* pc) { return pc ? pc->R : -1; }
 
 int kp_precond_set_tiles(kp_precond* pc, const int* tiles) {
   if (!pc || !tiles) return fail(KP_ERR_ARG, "kp_precond_set_tiles: NULL argument");
-  const int n = pc->precision == KP_FP64 ? kTiles64 : kTiles16;
+  const int n = 2 * (pc->precision == KP_FP64 ? kTiles64 : kTiles16);  // tiles x block orders
   for (int s = 0; s < 3; ++s)
     if (tiles[s] < -1 || tiles[s] >= n)
       return fail(KP_ERR_ARG, "kp_precond_set_tiles: tile index %d of stage %d not in [-1,%d)", tiles[s], s, n);

@@ -53,12 +53,13 @@ struct GemmArgs {
   int vec;                // 1: 16-byte operand loads are legal (alignment and K)
   long long a_lo;         // > 0: A = A[.., k] + A[.., a_lo + k] (hi + lo planes)
   const double* out_div;  // non-null: results are divided by *out_div
+  int order;              // block-to-tile order (tile_of)
 };
 
 GemmArgs gemm_args(const void* A, const void* B, void* C, long long M, long long Nn, long long K,
                    long long lda, long long ldb, long long sAb, long long sBb, OutMap om,
                    const int* done, long long a_lo = 0, const double* out_div = nullptr) {
-  return GemmArgs{A, B, C, (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0, a_lo, out_div};
+  return GemmArgs{A, B, C, (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0, a_lo, out_div, 0};
 }
 
 __device__ __forceinline__ long long out_addr(const OutMap& o, int m, int n, int b) {
@@ -66,14 +67,29 @@ __device__ __forceinline__ long long out_addr(const OutMap& o, int m, int n, int
          (long long)b * o.sb;
 }
 
-// Block-to-tile map over a 1D grid of Mt x Nt tiles (z = batch), column tile
-// fastest: concurrently resident blocks sweep along the data operand, and the
-// (small) circulant operand stays in every L2.  (An XCD-grouped order that
-// keeps the row tiles of one column tile together measured slower.)
-__device__ __forceinline__ void tile_of(int Mt, int& mt, int& nt) {
-  const int Nt = gridDim.x / Mt;
-  nt = blockIdx.x % Nt;
-  mt = blockIdx.x / Nt;
+// Block-to-tile map over a 1D grid of Mt x Nt tiles (z = batch).
+//  order 0: column tile fastest in launch order; concurrently resident blocks
+//           sweep along the data operand and the (small) circulant operand
+//           stays in every L2.
+//  order 1: the hardware deals the blocks of a launch round-robin to the eight
+//           XCDs (block b to XCD b % 8), each with its own L2.  Block b takes
+//           tile t = (b % 8) * (G / 8) + b / 8 with tiles numbered row tile
+//           fastest, so the Mt blocks that share one column tile of the data
+//           operand run on one XCD at about the same time and that tile
+//           crosses from HBM into that L2 once.  (G not a multiple of 8: row
+//           tile fastest in launch order.)
+// The autotuner times both orders.
+__device__ __forceinline__ void tile_of(int Mt, int order, int& mt, int& nt) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (order == 0) {
+    const int Nt = G / Mt;
+    nt = b % Nt;
+    mt = b / Nt;
+  } else {
+    const int t = (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
+    mt = t % Mt;
+    nt = t / Mt;
+  }
 }
 
 __device__ __forceinline__ bf16_t f32_to_bf16_rne(float x) {
@@ -113,7 +129,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   const double* __restrict__ B = (const double*)g.B + (long long)bz * g.sBb;
   double* __restrict__ C = (double*)g.C;
   int mt, nt;
-  tile_of((g.M + BM - 1) / BM, mt, nt);
+  tile_of((g.M + BM - 1) / BM, g.order, mt, nt);
   const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -183,28 +199,38 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 }
 
 // ---------------------------------------------------- BF16 / FP16 MFMA
-// 256 threads = 2 x 2 wavefronts, block tile BM x BN, K tile 64 (two
-// 16x16x32 steps).  Operands move as 16-byte vectors of eight 16-bit values;
-// LDS rows are padded by 16 bytes (conflict-free 16-byte fragment reads).
-// With SPLIT the A tile is staged twice (hi and lo planes) and every B
-// fragment feeds two MFMAs.  The next K tile is fetched into registers while
-// the current one is multiplied.
+// 256 threads = 2 x 2 wavefronts, block tile BM x BN, K tile BK (BK/32
+// 16x16x32 steps).  Operands move as 16-byte vectors of eight 16-bit values.
+// LDS: with BK = 64 a row is 128 bytes = eight 16-byte chunks and chunk c of
+// row r is stored at slot c ^ (r & 7) (no padding), so that the eight rows
+// read by one fragment load hit eight different chunk slots; with BK = 32
+// rows are padded by 16 bytes.  With SPLIT the A tile is staged twice (hi
+// and lo planes) and every B fragment feeds two MFMAs.  The next K tile is
+// fetched into registers while the current one is multiplied.
 template <int BM, int BN, int BK, bool F16, bool SPLIT, typename TO>
 __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   if (g.done && *g.done) return;
-  constexpr int LDK = BK + 8;
+  constexpr bool SWZ = BK == 64;
+  constexpr int LDK = SWZ ? BK : BK + 8;
+  auto slot = [](int row, int ch) { return SWZ ? ((ch ^ (row & 7)) * 8) : ch * 8; };
   constexpr int NP = SPLIT ? 2 : 1;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int VA = BM * BK / 8 / 256, VB = BN * BK / 8 / 256;  // 16-byte vectors per thread
-  __shared__ __attribute__((aligned(16))) bf16_t As[NP][BM][LDK];
-  __shared__ __attribute__((aligned(16))) bf16_t Bs[BN][LDK];
+  // Operand tiles; after the K loop the same memory stages the output.
+  constexpr int VL = 16 / (int)sizeof(TO);  // output elements per 16-byte vector
+  constexpr int LDO = WN + VL;              // padded staging row of one wave
+  constexpr int OP_BYTES = (NP * BM + BN) * LDK * 2;
+  constexpr int STG_BYTES = 4 * 16 * LDO * (int)sizeof(TO);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
+  auto As = reinterpret_cast<bf16_t(*)[BM][LDK]>(smem);
+  auto Bs = reinterpret_cast<bf16_t(*)[LDK]>(smem + NP * BM * LDK * 2);
   const int bz = blockIdx.z;
   const bf16_t* __restrict__ A = (const bf16_t*)g.A + (long long)bz * g.sAb;
   const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
   TO* __restrict__ C = (TO*)g.C;
   int mt, nt;
-  tile_of((g.M + BM - 1) / BM, mt, nt);
+  tile_of((g.M + BM - 1) / BM, g.order, mt, nt);
   const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -254,28 +280,33 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int t = 0; t < VA; ++t) {
-        const int e = tid + 256 * t;
-        *(u32x4*)&As[p][e / (BK / 8)][(e % (BK / 8)) * 8] = ra[p][t];
+        const int e = tid + 256 * t, row = e / (BK / 8);
+        *(u32x4*)&As[p][row][slot(row, e % (BK / 8))] = ra[p][t];
       }
 #pragma unroll
     for (int t = 0; t < VB; ++t) {
-      const int e = tid + 256 * t;
-      *(u32x4*)&Bs[e / (BK / 8)][(e % (BK / 8)) * 8] = rb[t];
+      const int e = tid + 256 * t, row = e / (BK / 8);
+      *(u32x4*)&Bs[row][slot(row, e % (BK / 8))] = rb[t];
     }
     __syncthreads();
     if (k0 + BK < g.K) load(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 32) {
+      const int ch = ks / 8 + (lane >> 4);
       u32x4 bfr[TN];
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
-        bfr[j] = *(const u32x4*)&Bs[wn * WN + j * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+      for (int j = 0; j < TN; ++j) {
+        const int row = wn * WN + j * 16 + (lane & 15);
+        bfr[j] = *(const u32x4*)&Bs[row][slot(row, ch)];
+      }
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         u32x4 af[TM];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-          af[i] = *(const u32x4*)&As[p][wm * WM + i * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+        for (int i = 0; i < TM; ++i) {
+          const int row = wm * WM + i * 16 + (lane & 15);
+          af[i] = *(const u32x4*)&As[p][row][slot(row, ch)];
+        }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -284,21 +315,36 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
     }
     __syncthreads();
   }
+  // Epilogue: every wave passes its 16 x WN accumulator strips through LDS
+  // and writes them as 16-byte vectors along n, which is contiguous in memory
+  // whenever sn2 = 1 and the vector stays inside one run of nd columns.
   const float oscale = g.out_div ? (float)(1.0 / *g.out_div) : 1.0f;
+  TO* stg = reinterpret_cast<TO*>(smem) + wid * 16 * LDO;
+  constexpr int VPR = WN / VL;  // vectors per staged row
+  const bool contig = g.om.sn2 == 1;
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
+  for (int i = 0; i < TM; ++i) {
     // v_mfma_f32_16x16x32_{bf16,f16} result: item v of lane l is row 4(l/16) + v, column l%16.
-    const int n = n0 + wn * WN + j * 16 + (lane & 15);
-    if (n >= g.Nn) continue;
-    const long long cbase = (long long)(n / g.om.nd) * g.om.sn1 + (long long)(n % g.om.nd) * g.om.sn2 +
-                            (long long)bz * g.om.sb;
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + v;
-        if (m < g.M) C[cbase + (long long)m * g.om.sm] = cvt_out<TO, F16>(acc[i][j][v] * oscale);
+      for (int v = 0; v < 4; ++v)
+        stg[(4 * (lane >> 4) + v) * LDO + j * 16 + (lane & 15)] = cvt_out<TO, F16>(acc[i][j][v] * oscale);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16 * VPR / 64; ++t) {
+      const int e = lane + 64 * t, r = e / VPR, c = (e % VPR) * VL;
+      const int m = m0 + wm * WM + i * 16 + r, n = n0 + wn * WN + c;
+      if (m >= g.M || n >= g.Nn) continue;
+      const TO* src = stg + r * LDO + c;
+      TO* dst = C + out_addr(g.om, m, n, bz);
+      if (contig && n + VL <= g.Nn && n % g.om.nd + VL <= g.om.nd && ((uintptr_t)dst & 15u) == 0) {
+        *(u32x4*)dst = *(const u32x4*)src;
+      } else {
+        for (int q = 0; q < VL && n + q < g.Nn; ++q) C[out_addr(g.om, m, n + q, bz)] = src[q];
       }
+    }
+    __syncthreads();
   }
 }
 
@@ -327,9 +373,11 @@ void launch64(kp_context* ctx, const GemmArgs& g, int batch) {
   hipLaunchKernelGGL((k_gemm_f64<BM, BN>), grid, dim3(256), 0, ctx->stream, g);
 }
 
-int run_gemm_f64(kp_context* ctx, const GemmArgs& g, int batch, int cfg) {
-  if (cfg < 0 || cfg >= kTiles64) cfg = heuristic64(g);
-  switch (cfg) {
+// cfg = tile + kTiles64 * order; out of range: size heuristic, order 0.
+int run_gemm_f64(kp_context* ctx, GemmArgs g, int batch, int cfg) {
+  if (cfg < 0 || cfg >= 2 * kTiles64) cfg = heuristic64(g);
+  g.order = cfg / kTiles64;
+  switch (cfg % kTiles64) {
     case 0: launch64<64, 64>(ctx, g, batch); break;
     case 1: launch64<128, 64>(ctx, g, batch); break;
     case 2: launch64<64, 128>(ctx, g, batch); break;
@@ -351,12 +399,14 @@ void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
   }
 }
 
+// cfg = tile + kTiles16 * order; out of range: size heuristic, order 0.
 template <typename TO>
 int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
   g.vec = (g.K % 8 == 0) && (g.lda % 8 == 0) && (g.ldb % 8 == 0) && (g.sAb % 8 == 0) &&
           (g.sBb % 8 == 0) && (g.a_lo % 8 == 0) && aligned16(g.A) && aligned16(g.B);
-  if (cfg < 0 || cfg >= kTiles16) cfg = heuristic16(g, batch);
-  switch (cfg) {
+  if (cfg < 0 || cfg >= 2 * kTiles16) cfg = heuristic16(g, batch);
+  g.order = cfg / kTiles16;
+  switch (cfg % kTiles16) {
     case 0: launch16<64, 64, 64, TO>(ctx, g, batch, f16); break;
     case 1: launch16<128, 64, 64, TO>(ctx, g, batch, f16); break;
     case 2: launch16<64, 128, 64, TO>(ctx, g, batch, f16); break;
@@ -455,7 +505,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* 
                      : make_stages(pc->N, pc->R, X, pc->a1_64, pc->c2_64, pc->b3_64, T, U, Z, nullptr, 1,
                                    nullptr);
   const bool f16 = pc->precision == KP_MIXED_FP16;
-  const int ncfg = sixteen ? kTiles16 : kTiles64;
+  const int ntile = sixteen ? kTiles16 : kTiles64, ncfg = 2 * ntile;
   int n = 0;
   for (int st = 0; st < 3; ++st) {
     const GemmArgs& g = st == 0 ? s.s1 : (st == 1 ? s.s2 : s.s3);
@@ -479,9 +529,11 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* 
       if (table && n < cap) {
         kp_tile_timing& e = table[n];
         e.stage = st;
-        e.bm = sixteen ? kCfg16[c][0] : kCfg64[c][0];
-        e.bn = sixteen ? kCfg16[c][1] : kCfg64[c][1];
-        e.bk = sixteen ? kCfg16[c][2] : 16;
+        const int t = c % ntile;
+        e.bm = sixteen ? kCfg16[t][0] : kCfg64[t][0];
+        e.bn = sixteen ? kCfg16[t][1] : kCfg64[t][1];
+        e.bk = sixteen ? kCfg16[t][2] : 16;
+        e.order = c / ntile;
         e.ms = avg;
       }
       ++n;

@@ -299,9 +299,10 @@ def test_every_tile_configuration_matches(ctx, prec, tol):
     apply with the chosen tiles, on a ragged size (N = 72, R = 3)."""
     F = even_factors(72, 3, seed=72)
     pc = kp.Precond(ctx, 72, precision=prec, factors=F)
-    ncfg = 4 if prec == "fp64" else 8
+    ncfg = 2 * (4 if prec == "fp64" else 8)      # tile shapes x two block orders
     table = pc.autotune(reps=1)
-    assert len(table) == 3 * ncfg and all(t[4] > 0 for t in table)
+    assert len(table) == 3 * ncfg and all(t[5] > 0 for t in table)
+    assert {t[4] for t in table} == {0, 1}
     tuned = pc.tiles
     assert all(0 <= t < ncfg for t in tuned)
     x = random_field(72, seed=8)
