@@ -88,7 +88,9 @@ typedef struct {
   double relres_true;    /* ||f - K x|| / ||f|| in double at exit             */
   double relres_rec;     /* recursive residual ratio at exit                  */
   double rhs_mean;       /* mean removed from f                               */
-  double ms;             /* wall time of the solve on the stream (hipEvents)  */
+  double ms;             /* wall time of the solve on the stream (hipEvents); batched: of the batch */
+  int status;            /* kp_status of this solve (batched: of this system)  */
+  int pad_;
 } kp_solve_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -252,6 +254,33 @@ int kp_free_precond(kp_precond* pc);
 int pcg_solve(kp_context* ctx, const kp_coeff* coeff, const kp_precond* pc, int rhs,
               const double* f_dev, double* x_dev, const kp_solve_opts* opts,
               kp_solve_stats* stats);
+
+/* Batched corrector solves: the Monte-Carlo setting of Section 5, many
+ * realizations of the coefficient (of uneven L) with the three corrector
+ * problems of each (eq. DD_Eqn with f = f_1, f_2, f_3).  Instance i is
+ * (coeffs[i], preconds[i]) with coeffs[i]->N == preconds[i]->N; all handles
+ * belong to ctx and share one precision (mixed or FP64).  System 3 i + j
+ * (j = 0..2) solves corrector j+1 of instance i into x_dev[3 i + j] (device,
+ * N_i^3 doubles, caller-owned; read as the initial guess when opts->use_x0,
+ * always overwritten with the zero-mean solution).
+ * Instances that share a preconditioner form one group; every PCG step of a
+ * group runs as one launch over all its systems, the groups run as
+ * concurrent branches of one HIP graph that holds opts->check_every
+ * iterations (0: 16), and the graph is replayed until every system has
+ * stopped.  Convergence is decided per system on the device, by the true
+ * residual in double, and a stopped system's share of every launch returns
+ * at once (convergence mask).  The GEMM tiles are autotuned for each group's
+ * batch size on first use (kept in the preconditioner).
+ * stats (host, 3 n_inst, may be NULL) per system, with status KP_OK,
+ * KP_NOT_CONVERGED or KP_ERR_BREAKDOWN; ahom (host, 9 n_inst doubles, may be
+ * NULL) receives each instance's homogenized matrix (as
+ * kp_homogenized_matrix).  Returns KP_OK when every system converged,
+ * KP_NOT_CONVERGED when some reached maxit, KP_ERR_BREAKDOWN when some broke
+ * down (the other systems are solved and reported), or an error.
+ * Synchronizes the stream. */
+int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* const* coeffs,
+                      const kp_precond* const* preconds, double* const* x_dev,
+                      const kp_solve_opts* opts, kp_solve_stats* stats, double* ahom);
 
 /* Homogenized matrix of one realization (eq. Ahom3_m_entry_comp):
  *   ahom[i][j] = delta_ij mean(a) - h sum_p phi_i(p) f_j(p),  i,j = 1..3,

@@ -23,7 +23,7 @@ from ._lib import (KP_FP64, KP_MIXED_BF16, KP_MIXED_FP16, KP_NOT_CONVERGED, KP_O
                    KP_WARN_RHS_MEAN, PRECISIONS, KronPCGError, PrecondInfo, SolveOpts, SolveStats,
                    check, load)
 
-__all__ = ["Context", "Coeff", "Precond", "solve", "homogenized_matrix", "stiffness_apply",
+__all__ = ["Context", "Coeff", "Precond", "solve", "solve_batched", "homogenized_matrix", "stiffness_apply",
            "lowrank_factors", "KronPCGError", "PRECISIONS", "KP_FP64", "KP_MIXED_BF16",
            "KP_MIXED_FP16", "KP_OK", "KP_NOT_CONVERGED", "KP_WARN_RHS_MEAN"]
 
@@ -240,6 +240,36 @@ def solve(ctx: Context, coeff: Coeff, precond: Precond, rhs: int = 1, f=None, x=
                           C.byref(opts), C.byref(stats))
     check(st, allow=(KP_OK, KP_NOT_CONVERGED, KP_WARN_RHS_MEAN))
     return x, stats.as_dict(), st
+
+
+def solve_batched(ctx: Context, coeffs, preconds, xs=None, tol: float = 1e-8, maxit: int = 2000,
+                  replace_every: int | None = None, use_x0: bool = False, check_every: int = 0,
+                  want_ahom: bool = True):
+    """pcg_solve_batched: the three correctors of every instance (coeffs[i], preconds[i]).
+
+    xs: optional list of 3 * len(coeffs) float64 CUDA tensors (N_i, N_i, N_i) (initial
+    guesses with use_x0).  Returns (xs, [stats dict per system], ahom (n, 3, 3) or None, status)."""
+    import torch
+    n = len(coeffs)
+    if len(preconds) != n:
+        raise ValueError("one preconditioner per coefficient")
+    if xs is None:
+        xs = [torch.empty((c.N, c.N, c.N), dtype=torch.float64, device=f"cuda:{ctx.device}")
+              for c in coeffs for _ in range(3)]
+    if len(xs) != 3 * n:
+        raise ValueError("xs needs three tensors per instance")
+    if replace_every is None:
+        replace_every = 0 if coeffs[0].precision == KP_FP64 else 25
+    opts = SolveOpts(float(tol), int(maxit), int(replace_every), int(bool(use_x0)), int(check_every))
+    stats = (SolveStats * (3 * n))()
+    ch = (C.c_void_p * n)(*[c.handle for c in coeffs])
+    ph = (C.c_void_p * n)(*[p.handle for p in preconds])
+    xp = (C.c_void_p * (3 * n))(*[_ptr(x) for x in xs])
+    ah = (C.c_double * (9 * n))() if want_ahom else None
+    st = load().pcg_solve_batched(ctx.handle, n, ch, ph, xp, C.byref(opts), stats, ah)
+    check(st, allow=(KP_OK, KP_NOT_CONVERGED))
+    A = np.frombuffer(ah, dtype=np.float64).reshape(n, 3, 3).copy() if want_ahom else None
+    return xs, [s.as_dict() for s in stats], A, st
 
 
 def homogenized_matrix(ctx: Context, coeff: Coeff, phis) -> np.ndarray:

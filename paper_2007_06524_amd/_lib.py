@@ -45,7 +45,8 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("replacements", C.c_int), ("relres_true", C.c_double),
-                ("relres_rec", C.c_double), ("rhs_mean", C.c_double), ("ms", C.c_double)]
+                ("relres_rec", C.c_double), ("rhs_mean", C.c_double), ("ms", C.c_double),
+                ("status", C.c_int), ("pad_", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +92,9 @@ SIGNATURES = {
     "kp_free_precond": (C.c_int, [C.c_void_p]),
     "pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                             C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+    "pcg_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_void_p), C.POINTER(SolveOpts), C.POINTER(SolveStats),
+                                    C.POINTER(C.c_double)]),
     "kp_homogenized_matrix": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_double)]),
     "kp_last_error": (C.c_char_p, []),

@@ -54,10 +54,33 @@ __device__ __forceinline__ bf16_t to16(float x, int fp16) {
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
-// One block of 256 threads: totals of nvals values, then the PCG scalar logic.
+// Power of two bringing the RMS of r near 1 before 16-bit rounding (keeps FP16
+// inputs normal as the residual shrinks; exact to undo).
+__device__ double x16_scale_for(double rr, double n3) {
+  double sc = 1.0;
+  if (rr > 0.0 && finite(rr)) {
+    double e = rint(-0.5 * log2(rr / n3));
+    e = fmin(fmax(e, -120.0), 120.0);
+    sc = exp2(e);
+  }
+  return sc;
+}
+
+__device__ void stop(Scalars* s, int status) {
+  s->done = 1;
+  s->status = status;
+  if (status == 3) s->breakdown = 1;
+}
+
+// One block of 256 threads per system: totals of nvals values, then the PCG
+// scalar logic of `mode` for that system.
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int nparts,
                                                   int nvals, int mode, Scalars* s, double n3) {
+  const int b = blockIdx.x;
+  s += b;
+  partial += (size_t)b * nvals * nparts;
   if (s->done && mode != FIN_SUM && mode != FIN_FF) return;
+  if (mode == FIN_TRUE_CTL && !s->check) return;
   __shared__ double tot[8];
   for (int v = 0; v < nvals; ++v) {
     double acc = 0.0;
@@ -75,16 +98,19 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   switch (mode) {
     case FIN_SUM:
       break;
-    case FIN_FF:  // partials of k_sum2: (sum, sum of squares)
-      s->ff = tot[1];
+    case FIN_FF: {  // partials of k_sum2: (sum, sum of squares)
+      const double ff = tot[1];
+      s->ff = ff;
+      s->tol2ff *= ff;  // tol^2 -> tol^2 ||f||^2 (the single solver writes it afterwards)
+      if (!(ff > 0.0)) stop(s, 1);  // zero right-hand side: x = 0
       break;
+    }
     case FIN_ALPHA: {
       const double pq = tot[0];
       s->pq = pq;
       s->x16_scale = s->x16_scale_next;  // r of this iteration is rounded with this scale
       if (!(pq > 0.0) || !finite(pq)) {
-        s->breakdown = 1;
-        s->done = 1;
+        stop(s, 3);
         s->alpha = 0.0;
       } else {
         s->alpha = s->rho / pq;
@@ -96,21 +122,50 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
       const double rr = tot[0];
       s->rr = rr;
       if (mode == FIN_RR) s->iters += 1;
-      // Power of two bringing the RMS of r near 1 before 16-bit rounding (keeps
-      // FP16 inputs normal as the residual shrinks; exact to undo).
-      double sc = 1.0;
-      if (rr > 0.0 && finite(rr)) {
-        double e = rint(-0.5 * log2(rr / n3));
-        e = fmin(fmax(e, -120.0), 120.0);
-        sc = exp2(e);
-      }
+      const double sc = x16_scale_for(rr, n3);
       s->x16_scale_next = sc;
       if (mode == FIN_RR_NOCOUNT) s->x16_scale = sc;  // followed by a fresh conversion
       if (!finite(rr)) {
-        s->breakdown = 1;
-        s->done = 1;
+        stop(s, 3);
       } else if (rr <= s->tol2ff) {
         s->done = 1;
+        if (mode == FIN_RR_NOCOUNT) s->status = 1;  // a true residual: converged
+      }
+      break;
+    }
+    case FIN_RR_CTL: {
+      const double rr = tot[0];
+      s->rr = rr;
+      s->iters += 1;
+      s->x16_scale_next = x16_scale_for(rr, n3);
+      if (!finite(rr)) {
+        stop(s, 3);
+        break;
+      }
+      s->check = rr <= s->tol2ff || s->iters >= s->maxit ||
+                 (s->replace_every > 0 && s->iters % s->replace_every == 0);
+      if (s->check) s->rr_rec = rr;
+      break;
+    }
+    case FIN_TRUE_CTL: {
+      // r now holds f - K x in the iterate's precision; tot[0] = ||f - K x||^2 (double).
+      const double rr = tot[0];
+      s->check = 0;
+      if (!finite(rr)) {
+        stop(s, 3);
+        break;
+      }
+      s->rr = rr;
+      if (rr <= s->tol2ff) {
+        stop(s, 1);
+      } else if (s->iters >= s->maxit) {
+        stop(s, 2);
+      } else {
+        s->replaced = 1;
+        s->replacements += 1;
+        const double sc = x16_scale_for(rr, n3);
+        s->x16_scale = sc;
+        s->x16_scale_next = sc;
       }
       break;
     }
@@ -120,15 +175,16 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
       // tot: <r,z>, <q,z>, sum z, sum r, sum q
       const double mz = tot[2] / n3;
       const double rho_new = tot[0] - mz * tot[3];
+      const bool fr = mode == FIN_PREC_FR || s->replaced;
+      s->replaced = 0;
       s->mz = mz;
       if (!(rho_new > 0.0) || !finite(rho_new)) {
-        s->breakdown = 1;
-        s->done = 1;
+        stop(s, 3);
         break;
       }
       if (mode == FIN_PREC_INIT) {
         s->beta = 0.0;
-      } else if (s->flexible && mode == FIN_PREC) {
+      } else if (s->flexible && !fr) {
         // <z - mz, r_new - r_old> = -alpha <z - mz, q>
         s->beta = -s->alpha * (tot[1] - mz * tot[4]) / s->rho;
       } else {
@@ -172,13 +228,23 @@ __device__ __forceinline__ void st4(T* __restrict__ p, size_t i, const T (&v)[4]
   *(typename Vec4<T>::type*)(p + i) = t;
 }
 
+// Vector kernels: blockIdx.y is the system of the batch (Batch layout).
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, const T* __restrict__ p,
                                                    T* __restrict__ r, const T* __restrict__ q,
                                                    bf16_t* __restrict__ r16, int fp16,
                                                    const Scalars* __restrict__ s,
-                                                   double* __restrict__ partial, size_t n) {
+                                                   double* __restrict__ partial, size_t n,
+                                                   size_t vs) {
+  const int b = blockIdx.y;
+  s += b;
   if (s->done) return;
+  const size_t off = b * vs;
+  x += off;
+  p += off;
+  r += off;
+  q += off;
+  if (r16) r16 += off;
   const double alpha = s->alpha;
   const T ta = (T)alpha;
   const float sc = (float)s->x16_scale;
@@ -217,7 +283,7 @@ __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, const
     if (r16) r16[i] = to16((float)rn * sc, fp16);
     acc[0] += (double)rn * (double)rn;
   }
-  block_sums_store<1>(acc, partial + blockIdx.x, gridDim.x);
+  block_sums_store<1>(acc, partial + (size_t)b * gridDim.x + blockIdx.x, gridDim.x);
 }
 
 // <r,z>, <q,z>, sum z, sum r, sum q (q may be null on the first application).
@@ -225,8 +291,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prec_dots(const T* __restrict__ z, const T* __restrict__ r,
                                                    const T* __restrict__ q,
                                                    const Scalars* __restrict__ s,
-                                                   double* __restrict__ partial, size_t n) {
-  if (s->done) return;
+                                                   double* __restrict__ partial, size_t n,
+                                                   size_t vs) {
+  const int b = blockIdx.y;
+  if (s[b].done) return;
+  const size_t off = b * vs;
+  z += off;
+  r += off;
+  if (q) q += off;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const size_t stride = (size_t)gridDim.x * 256, n4 = n / 4;
   for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n4; c += stride) {
@@ -253,14 +325,19 @@ __global__ __launch_bounds__(256) void k_prec_dots(const T* __restrict__ z, cons
     acc[3] += ri;
     acc[4] += qi;
   }
-  block_sums_store<5>(acc, partial + blockIdx.x, gridDim.x);
+  block_sums_store<5>(acc, partial + (size_t)b * 5 * gridDim.x + blockIdx.x, gridDim.x);
 }
 
 // p = (z - mean(z)) + beta p  (beta = 0: restart, p may hold stale or uninitialized values)
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_p(const T* __restrict__ z, T* __restrict__ p,
-                                                  const Scalars* __restrict__ s, size_t n) {
+                                                  const Scalars* __restrict__ s, size_t n,
+                                                  size_t vs) {
+  const int b = blockIdx.y;
+  s += b;
   if (s->done) return;
+  z += b * vs;
+  p += b * vs;
   const T beta = (T)s->beta;
   const T mz = (T)s->mz;
   const bool restart = s->beta == 0.0;
@@ -279,18 +356,31 @@ __global__ __launch_bounds__(256) void k_update_p(const T* __restrict__ z, T* __
 }
 
 __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ a, size_t n,
-                                              double* __restrict__ partial) {
+                                              double* __restrict__ partial, size_t vs) {
+  const int b = blockIdx.y;
+  a += b * vs;
   double acc[2] = {0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const double v = a[i];
     acc[0] += v;
     acc[1] += v * v;
   }
-  block_sums_store<2>(acc, partial + blockIdx.x, gridDim.x);
+  block_sums_store<2>(acc, partial + (size_t)b * 2 * gridDim.x + blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_copy_project(const double* __restrict__ f, double mean,
                                                       double* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    out[i] = f[i] - mean;
+}
+
+__global__ __launch_bounds__(256) void k_project_s(const double* __restrict__ f,
+                                                   double* __restrict__ out, size_t n,
+                                                   const Scalars* __restrict__ s, size_t vs) {
+  const int b = blockIdx.y;
+  const double mean = s[b].sums[0] / (double)n;
+  f += b * vs;
+  out += b * vs;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
     out[i] = f[i] - mean;
 }
@@ -315,9 +405,13 @@ __global__ __launch_bounds__(256) void k_cast_to16(const double* __restrict__ a,
 
 __global__ __launch_bounds__(256) void k_cast32_to16(const float* __restrict__ a,
                                                      bf16_t* __restrict__ b, size_t n, int fp16,
-                                                     const Scalars* __restrict__ s) {
-  if (s && s->done) return;
-  const float sc = s ? (float)s->x16_scale : 1.0f;
+                                                     const Scalars* __restrict__ s, int gate,
+                                                     size_t vs) {
+  const int bi = blockIdx.y;
+  if (s && !gate_open(s[bi], gate)) return;
+  const float sc = s ? (float)s[bi].x16_scale : 1.0f;
+  a += bi * vs;
+  b += bi * vs;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
     b[i] = to16(a[i] * sc, fp16);
 }
@@ -325,6 +419,20 @@ __global__ __launch_bounds__(256) void k_cast32_to16(const float* __restrict__ a
 __global__ __launch_bounds__(256) void k_fill(double* __restrict__ a, double v, size_t n) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
     a[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_count_active(const Scalars* __restrict__ s, int nsys,
+                                                      int* __restrict__ out) {
+  int c = 0;
+  for (int i = threadIdx.x; i < nsys; i += 256) c += s[i].done ? 0 : 1;
+  __shared__ int red[256];
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
 }
 
 // Nine dot products <phi_i, f_j> and the sum of the cell values.
@@ -360,12 +468,21 @@ int grid_for(size_t n) {
   return (int)b;
 }
 
+// Blocks per system of the reducing vector kernels: about four 4-element
+// steps per thread, at most kRedBlocks.
+int red_blocks(size_t n) {
+  size_t b = (n + 4095) / 4096;
+  if (b > (size_t)kRedBlocks) b = kRedBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
 }  // namespace
 
 int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nvals, int mode,
-                    Scalars* s, size_t n3) {
+                    Scalars* s, size_t n3, int nsys) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, ctx->stream, partial, nparts, nvals, mode,
+  hipLaunchKernelGGL(k_finalize, dim3(nsys), dim3(256), 0, ctx->stream, partial, nparts, nvals, mode,
                      s, (double)n3);
   KP_HIP(hipGetLastError());
   return KP_OK;
@@ -373,11 +490,12 @@ int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nval
 
 template <typename T>
 int launch_update_xr(kp_context* ctx, double* x, const T* p, T* r, const T* q, bf16_t* r16,
-                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n) {
+                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n,
+                     const Batch& bt) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
-  const int g = kRedBlocks;
-  hipLaunchKernelGGL(k_update_xr<T>, dim3(g), dim3(256), 0, ctx->stream, x, p, r, q, r16, fp16, s,
-                     partial, n);
+  const int g = red_blocks(n);
+  hipLaunchKernelGGL(k_update_xr<T>, dim3(g, bt.nsys), dim3(256), 0, ctx->stream, x, p, r, q, r16,
+                     fp16, s, partial, n, bt.vs);
   KP_HIP(hipGetLastError());
   *nparts = g;
   return KP_OK;
@@ -385,38 +503,46 @@ int launch_update_xr(kp_context* ctx, double* x, const T* p, T* r, const T* q, b
 
 template <typename T>
 int launch_prec_dots(kp_context* ctx, const T* z, const T* r, const T* q, const Scalars* s,
-                     double* partial, int* nparts, size_t n) {
+                     double* partial, int* nparts, size_t n, const Batch& bt) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
-  const int g = kRedBlocks;
-  hipLaunchKernelGGL(k_prec_dots<T>, dim3(g), dim3(256), 0, ctx->stream, z, r, q, s, partial, n);
+  const int g = red_blocks(n);
+  hipLaunchKernelGGL(k_prec_dots<T>, dim3(g, bt.nsys), dim3(256), 0, ctx->stream, z, r, q, s, partial,
+                     n, bt.vs);
   KP_HIP(hipGetLastError());
   *nparts = g;
   return KP_OK;
 }
 
 template <typename T>
-int launch_update_p(kp_context* ctx, const T* z, T* p, const Scalars* s, size_t n) {
+int launch_update_p(kp_context* ctx, const T* z, T* p, const Scalars* s, size_t n,
+                    const Batch& bt) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
-  hipLaunchKernelGGL(k_update_p<T>, dim3(grid_for(n)), dim3(256), 0, ctx->stream, z, p, s, n);
+  hipLaunchKernelGGL(k_update_p<T>, dim3(red_blocks(n), bt.nsys), dim3(256), 0, ctx->stream, z, p, s,
+                     n, bt.vs);
   KP_HIP(hipGetLastError());
   return KP_OK;
 }
 
 template int launch_update_xr<double>(kp_context*, double*, const double*, double*, const double*,
-                                      bf16_t*, int, const Scalars*, double*, int*, size_t);
+                                      bf16_t*, int, const Scalars*, double*, int*, size_t,
+                                      const Batch&);
 template int launch_update_xr<float>(kp_context*, double*, const float*, float*, const float*,
-                                     bf16_t*, int, const Scalars*, double*, int*, size_t);
+                                     bf16_t*, int, const Scalars*, double*, int*, size_t,
+                                     const Batch&);
 template int launch_prec_dots<double>(kp_context*, const double*, const double*, const double*,
-                                      const Scalars*, double*, int*, size_t);
+                                      const Scalars*, double*, int*, size_t, const Batch&);
 template int launch_prec_dots<float>(kp_context*, const float*, const float*, const float*,
-                                     const Scalars*, double*, int*, size_t);
-template int launch_update_p<double>(kp_context*, const double*, double*, const Scalars*, size_t);
-template int launch_update_p<float>(kp_context*, const float*, float*, const Scalars*, size_t);
+                                     const Scalars*, double*, int*, size_t, const Batch&);
+template int launch_update_p<double>(kp_context*, const double*, double*, const Scalars*, size_t,
+                                     const Batch&);
+template int launch_update_p<float>(kp_context*, const float*, float*, const Scalars*, size_t,
+                                    const Batch&);
 
-int launch_sum2(kp_context* ctx, const double* a, size_t n, double* partial, int* nparts) {
+int launch_sum2(kp_context* ctx, const double* a, size_t n, double* partial, int* nparts,
+                const Batch& bt) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
-  const int g = kRedBlocks;
-  hipLaunchKernelGGL(k_sum2, dim3(g), dim3(256), 0, ctx->stream, a, n, partial);
+  const int g = red_blocks(n);
+  hipLaunchKernelGGL(k_sum2, dim3(g, bt.nsys), dim3(256), 0, ctx->stream, a, n, partial, bt.vs);
   KP_HIP(hipGetLastError());
   *nparts = g;
   return KP_OK;
@@ -425,6 +551,15 @@ int launch_sum2(kp_context* ctx, const double* a, size_t n, double* partial, int
 int launch_copy_project_f(kp_context* ctx, const double* f, double mean, double* out, size_t n) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
   hipLaunchKernelGGL(k_copy_project, dim3(grid_for(n)), dim3(256), 0, ctx->stream, f, mean, out, n);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int launch_project_s(kp_context* ctx, const double* f, double* out, size_t n, const Scalars* s,
+                     const Batch& bt) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_project_s, dim3(red_blocks(n), bt.nsys), dim3(256), 0, ctx->stream, f, out, n,
+                     s, bt.vs);
   KP_HIP(hipGetLastError());
   return KP_OK;
 }
@@ -451,10 +586,10 @@ int launch_cast_to16(kp_context* ctx, const double* a, bf16_t* b, size_t n, int 
 }
 
 int launch_cast32_to16(kp_context* ctx, const float* a, bf16_t* b, size_t n, int fp16,
-                       const Scalars* s) {
+                       const Scalars* s, const Batch& bt, int gate) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
-  hipLaunchKernelGGL(k_cast32_to16, dim3(grid_for(n)), dim3(256), 0, ctx->stream, a, b, n, fp16,
-                     s);
+  hipLaunchKernelGGL(k_cast32_to16, dim3(red_blocks(n), bt.nsys), dim3(256), 0, ctx->stream, a, b, n,
+                     fp16, s, gate, bt.vs);
   KP_HIP(hipGetLastError());
   return KP_OK;
 }
@@ -462,6 +597,14 @@ int launch_cast32_to16(kp_context* ctx, const float* a, bf16_t* b, size_t n, int
 int launch_fill_f64(kp_context* ctx, double* a, double v, size_t n) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, ctx->stream, a, v, n);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
+int vector_parts(size_t n) { return red_blocks(n); }
+
+int launch_count_active(kp_context* ctx, const Scalars* s, int nsys, int* out) {
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, ctx->stream, s, nsys, out);
   KP_HIP(hipGetLastError());
   return KP_OK;
 }

@@ -266,6 +266,18 @@ static int upload_precond(kp_context* ctx, int N, int R, const double* factors, 
   return KP_OK;
 }
 
+int launch_ahom(kp_context* ctx, const kp_coeff* c, const double* const* phi, double* part,
+                double* out) {
+  const size_t n3 = (size_t)c->N * c->N * c->N;
+  const size_t nc = (size_t)c->L * c->L * c->L;
+  int np = 0;
+  KP_TRY(launch_multidot9(ctx, phi, c->f, n3, c->cells, nc, part, &np));
+  hipLaunchKernelGGL(k_ahom_final, dim3(1), dim3(256), 0, ctx->stream, (const double*)part, np,
+                     (double)nc, 1.0 / c->N, out);
+  KP_HIP(hipGetLastError());
+  return KP_OK;
+}
+
 }  // namespace kp
 
 using namespace kp;
@@ -522,7 +534,7 @@ int kp_precond_autotune(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timin
   if (pc->ctx != ctx) return fail(KP_ERR_STATE, "kp_precond_autotune: preconditioner of another context");
   if (reps < 1 || reps > 1000) return fail(KP_ERR_ARG, "kp_precond_autotune: reps must be 1..1000");
   KP_HIP(hipSetDevice(ctx->device));
-  KP_TRY(autotune_precond(ctx, pc, reps, table, table ? cap : 0, count));
+  KP_TRY(autotune_precond(ctx, pc, 1, reps, table, table ? cap : 0, count, pc->tile));
   KP_HIP(hipStreamSynchronize(ctx->stream));
   return KP_OK;
 }
@@ -549,7 +561,7 @@ int kp_precond_apply(kp_context* ctx, const kp_precond* pc, const double* r_dev,
   KP_TRY(ws_get(ctx, WS_X16, n3 * sizeof(bf16_t), &x16));
   KP_TRY(ws_get(ctx, WS_Z, n3 * sizeof(float), &z32));
   KP_TRY(launch_cast_to16(ctx, r_dev, (bf16_t*)x16, n3, pc->precision == KP_MIXED_FP16));
-  KP_TRY(launch_precond_16(ctx, pc, (const bf16_t*)x16, (float*)z32, nullptr, nullptr));
+  KP_TRY(launch_precond_16(ctx, pc, (const bf16_t*)x16, (float*)z32, nullptr));
   return launch_cast_f32_f64(ctx, (const float*)z32, z_dev, n3);
 }
 
@@ -558,16 +570,10 @@ int kp_homogenized_matrix(kp_context* ctx, const kp_coeff* c, const double* cons
   if (!ctx || !c || !phi_dev || !ahom) return fail(KP_ERR_ARG, "kp_homogenized_matrix: NULL argument");
   for (int i = 0; i < 3; ++i)
     if (!phi_dev[i]) return fail(KP_ERR_ARG, "kp_homogenized_matrix: phi[%d] is NULL", i);
-  const size_t n3 = (size_t)c->N * c->N * c->N;
-  const size_t nc = (size_t)c->L * c->L * c->L;
   void *part, *res;
   KP_TRY(ws_get(ctx, WS_PART, (size_t)kMaxPartials * 8 * sizeof(double), &part));
   KP_TRY(ws_get(ctx, WS_SCAL, sizeof(Scalars), &res));
-  int np = 0;
-  KP_TRY(launch_multidot9(ctx, phi_dev, c->f, n3, c->cells, nc, (double*)part, &np));
-  hipLaunchKernelGGL(k_ahom_final, dim3(1), dim3(256), 0, ctx->stream, (const double*)part, np,
-                     (double)nc, 1.0 / c->N, (double*)res);
-  KP_HIP(hipGetLastError());
+  KP_TRY(launch_ahom(ctx, c, phi_dev, (double*)part, (double*)res));
   KP_HIP(hipMemcpyAsync(ahom, res, 9 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   KP_HIP(hipStreamSynchronize(ctx->stream));
   return KP_OK;

@@ -43,10 +43,30 @@ struct Scalars {
   double x16_scale;       // power of two applied to r before its 16-bit rounding
   double x16_scale_next;  // the scale for the next conversion (from the newest ||r||)
   double sums[8]; // scratch results of the last multi-value reduction
+  double rr_rec;  // recursive ||r||^2 when the last true residual was taken
   int done;       // 1: converged (recursive test) or broken down; kernels then no-op
   int breakdown;  // 1: <p,Kp> <= 0, rho <= 0 or non-finite
   int iters;      // iterations completed
   int flexible;   // 1: Polak-Ribiere beta, 0: Fletcher-Reeves beta
+  // Device-side control of the batched solver (FIN_RR_CTL / FIN_TRUE_CTL):
+  int check;         // 1: take the true residual in this iteration
+  int replaced;      // 1: r was replaced by the true residual in this iteration
+  int status;        // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+  int maxit;         // iteration limit
+  int replace_every; // residual replacement period (0: only when the recursion converges)
+  int replacements;  // true residuals that replaced r
+};
+
+// A batch of `nsys` systems of one grid size.  System b keeps its vectors at
+// base + b * vs, reads the coefficient fields of realization b / per at
+// base + (b / per) * ws, uses the scalars s[b], and its reduction partials
+// occupy partial[b * nvals * nparts ...] (value v at + v * nparts).  The
+// default is one system.
+struct Batch {
+  int nsys = 1;
+  int per = 1;
+  size_t vs = 0;
+  size_t ws = 0;
 };
 
 // Grow-only device buffer owned by a context.
@@ -76,9 +96,24 @@ enum FinMode {
   FIN_RR_NOCOUNT = 3,
   FIN_PREC = 4,     // sums of <r,z>, <q,z>, sum z, sum r, sum q -> rho, beta, mz
   FIN_PREC_INIT = 5,// same, beta = 0 (restart)
-  FIN_FF = 6,       // ff = second total (sum of squares from k_sum2)
-  FIN_PREC_FR = 7   // as FIN_PREC with the Fletcher-Reeves beta (after a residual replacement)
+  FIN_FF = 6,       // ff = second total (sum of squares from k_sum2); tol2ff *= ff
+  FIN_PREC_FR = 7,  // as FIN_PREC with the Fletcher-Reeves beta (after a residual replacement)
+  FIN_RR_CTL = 8,   // as FIN_RR, but a small recursive residual (or a replacement period, or
+                    // the iteration limit) only requests a true residual (check = 1)
+  FIN_TRUE_CTL = 9  // after the true residual: converge, stop at the limit, or replace r
 };
+
+// Which systems a gated kernel works on.
+enum Gate {
+  GATE_ACTIVE = 0,   // systems not done
+  GATE_CHECK = 1,    // systems with check set
+  GATE_REPLACED = 2  // systems with replaced set
+};
+
+__device__ __forceinline__ bool gate_open(const Scalars& s, int gate) {
+  if (s.done) return false;
+  return gate == GATE_ACTIVE || (gate == GATE_CHECK ? s.check != 0 : s.replaced != 0);
+}
 
 struct TimerRec {
   int id;
@@ -148,6 +183,8 @@ struct kp_precond {
   kp::bf16_t* b3_16 = nullptr;  // RN x 2N
   kp_precond_info info{};
   int tile[3] = {-1, -1, -1};   // tile configuration per GEMM stage (-1: size heuristic)
+  int tile_batch[3] = {-1, -1, -1};  // the same, tuned for batched solves
+  int tuned_nsys = 0;                // batch size tile_batch was tuned for (0: not tuned)
 };
 
 namespace kp {
@@ -165,52 +202,79 @@ constexpr int kMaxPartials = 65536;
 constexpr int kTiles64 = 4;
 constexpr int kTiles16 = 8;
 
-int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* table, int cap,
-                     int* count);
+// Times every tile configuration for a batch of nsys systems on scratch T, U,
+// X, Z (NULL: the context workspace, nsys = 1) and stores the fastest in tiles[3].
+int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_tile_timing* table,
+                     int cap, int* count, int* tiles, void* T = nullptr, void* U = nullptr,
+                     void* X = nullptr, void* Z = nullptr);
 
 // ---- launchers (each returns a kp_status) ----------------------------------
 int launch_assemble(kp_context* ctx, kp_coeff* c);
 // Sets *bad (device int, zeroed by the caller) when a cell is not finite or <= 0.
 int launch_validate_cells(kp_context* ctx, const double* cells, size_t n, int* bad);
 
-// Stencil q = K p (or out = f - K p when resid), block partials of <p,q> (or ||out||^2).
+// Stencil q = K p (or out = f - K p when f is given), block partials of <p,q>
+// (or ||out||^2).  s (nullable) gates the systems (gate: enum Gate).
 int launch_stencil_f64(kp_context* ctx, const double* p, const double* w, const double* f,
-                       double* out, double* partial, int* nparts, const int* done, int N);
+                       double* out, double* partial, int* nparts, const Scalars* s, int N,
+                       const Batch& bt = Batch(), int gate = GATE_ACTIVE);
 int launch_stencil_f32(kp_context* ctx, const float* p, const float* w, float* out,
-                       double* partial, int* nparts, const int* done, int N);
+                       double* partial, int* nparts, const Scalars* s, int N,
+                       const Batch& bt = Batch());
 int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* w, const double* f,
-                            float* out, double* partial, int* nparts, const int* done, int N);
+                            float* out, double* partial, int* nparts, const Scalars* s, int N,
+                            const Batch& bt = Batch(), int gate = GATE_ACTIVE);
 
+// One block per system: totals of nvals values, then the scalar update `mode`.
 int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nvals, int mode,
-                    Scalars* s, size_t n3);
+                    Scalars* s, size_t n3, int nsys = 1);
 
 // Preconditioner: z = sum_k (C1 x C2 x C3) x for x in the precision's input type.
+// tiles: the tile configuration per stage (NULL: the preconditioner's own).
 int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, double* z,
-                       const int* done);
-// x16 holds s * r rounded to 16 bits, with s = *scale (power of two; NULL means 1);
-// the result z is divided by s again.
+                       const Scalars* s, const Batch& bt = Batch(), void* T = nullptr,
+                       void* U = nullptr, const int* tiles = nullptr);
+// x16 holds c * r rounded to 16 bits, with c = s[b].x16_scale when s is given
+// (a power of two; 1 without s); the result z is divided by c again.
 int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, float* z,
-                      const int* done, const double* scale);
+                      const Scalars* s, const Batch& bt = Batch(), void* T = nullptr,
+                      void* U = nullptr, const int* tiles = nullptr);
 
-// Vector kernels (double vectors: T = double; mixed: T = float).
+// Vector kernels (double vectors: T = double; mixed: T = float).  All take a
+// batch: vectors at + b * bt.vs, scalars s + b.
 int launch_copy_project_f(kp_context* ctx, const double* f, double mean, double* out, size_t n);
-int launch_sum2(kp_context* ctx, const double* a, size_t n, double* partial, int* nparts);
+// out = f - s[b].sums[0] / n (the mean from a FIN_SUM / FIN_FF reduction).
+int launch_project_s(kp_context* ctx, const double* f, double* out, size_t n, const Scalars* s,
+                     const Batch& bt);
+int launch_sum2(kp_context* ctx, const double* a, size_t n, double* partial, int* nparts,
+                const Batch& bt = Batch());
 int launch_cast_f64_f32(kp_context* ctx, const double* a, float* b, size_t n);
 int launch_cast_f32_f64(kp_context* ctx, const float* a, double* b, size_t n);
 int launch_cast_to16(kp_context* ctx, const double* a, bf16_t* b, size_t n, int fp16);
-// b = 16-bit(a * s->x16_scale) (scale 1 when s is NULL); skipped when s->done.
+// b = 16-bit(a * s->x16_scale) (scale 1 when s is NULL); gated by s.
 int launch_cast32_to16(kp_context* ctx, const float* a, bf16_t* b, size_t n, int fp16,
-                       const Scalars* s);
+                       const Scalars* s, const Batch& bt = Batch(), int gate = GATE_ACTIVE);
 int launch_fill_f64(kp_context* ctx, double* a, double v, size_t n);
 
 template <typename T>
 int launch_update_xr(kp_context* ctx, double* x, const T* p, T* r, const T* q, bf16_t* r16,
-                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n);
+                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n,
+                     const Batch& bt = Batch());
 template <typename T>
 int launch_prec_dots(kp_context* ctx, const T* z, const T* r, const T* q, const Scalars* s,
-                     double* partial, int* nparts, size_t n);
+                     double* partial, int* nparts, size_t n, const Batch& bt = Batch());
 template <typename T>
-int launch_update_p(kp_context* ctx, const T* z, T* p, const Scalars* s, size_t n);
+int launch_update_p(kp_context* ctx, const T* z, T* p, const Scalars* s, size_t n,
+                    const Batch& bt = Batch());
+// *out = number of systems of s[0..nsys) that are not done.
+int launch_count_active(kp_context* ctx, const Scalars* s, int nsys, int* out);
+// Per-system partial counts: the most a stencil launch writes at grid size N,
+// and what a reducing vector kernel writes per value for n elements.
+int stencil_parts_max(int N);
+int vector_parts(size_t n);
+// a_hom (9 doubles at out, device) of realization c from its three correctors.
+int launch_ahom(kp_context* ctx, const kp_coeff* c, const double* const* phi, double* part,
+                double* out);
 int launch_multidot9(kp_context* ctx, const double* const* phi, const double* f, size_t n,
                      const double* cells, size_t ncells, double* partial, int* nparts);
 

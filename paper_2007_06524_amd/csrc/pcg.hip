@@ -36,7 +36,6 @@ struct Solver {
   int N;
   size_t n3;
   Scalars* s;        // device
-  int* done;         // &s->done
   double* part;
   double* fp;        // projected right-hand side (double)
   double* x;
@@ -76,13 +75,13 @@ int true_residual(Solver& S, bool into_r) {
 // z = M r; rho, mean(z), beta from the dot products; p = (z - mz) + beta p.
 int precondition_and_update(Solver& S, int fin_mode, bool have_q) {
   if (S.mixed) {
-    KP_TRY(launch_precond_16(S.ctx, S.pc, S.x16, (float*)S.z, S.done, &S.s->x16_scale));
+    KP_TRY(launch_precond_16(S.ctx, S.pc, S.x16, (float*)S.z, S.s));
     KP_TRY(launch_prec_dots<float>(S.ctx, (const float*)S.z, (const float*)S.r,
                                    have_q ? (const float*)S.q : nullptr, S.s, S.part, &S.np, S.n3));
     KP_TRY(fin(S, 5, fin_mode));
     return launch_update_p<float>(S.ctx, (const float*)S.z, (float*)S.p, S.s, S.n3);
   }
-  KP_TRY(launch_precond_f64(S.ctx, S.pc, (const double*)S.r, (double*)S.z, S.done));
+  KP_TRY(launch_precond_f64(S.ctx, S.pc, (const double*)S.r, (double*)S.z, S.s));
   KP_TRY(launch_prec_dots<double>(S.ctx, (const double*)S.z, (const double*)S.r,
                                   have_q ? (const double*)S.q : nullptr, S.s, S.part, &S.np, S.n3));
   KP_TRY(fin(S, 5, fin_mode));
@@ -91,7 +90,7 @@ int precondition_and_update(Solver& S, int fin_mode, bool have_q) {
 
 int iteration(Solver& S, bool replace) {
   if (S.mixed) {
-    KP_TRY(launch_stencil_f32(S.ctx, (const float*)S.p, S.c->w32, (float*)S.q, S.part, &S.np, S.done, S.N));
+    KP_TRY(launch_stencil_f32(S.ctx, (const float*)S.p, S.c->w32, (float*)S.q, S.part, &S.np, S.s, S.N));
     KP_TRY(fin(S, 1, FIN_ALPHA));
     KP_TRY(launch_update_xr<float>(S.ctx, S.x, (const float*)S.p, (float*)S.r, (const float*)S.q,
                                    S.x16, S.fp16, S.s, S.part, &S.np, S.n3));
@@ -99,13 +98,13 @@ int iteration(Solver& S, bool replace) {
     if (replace) {
       void* r64;
       KP_TRY(ws_get(S.ctx, WS_TMP64B, S.n3 * sizeof(double), &r64));
-      KP_TRY(launch_resid_f64_to_f32(S.ctx, S.x, S.c->w64, S.fp, (float*)S.r, S.part, &S.np, S.done, S.N));
+      KP_TRY(launch_resid_f64_to_f32(S.ctx, S.x, S.c->w64, S.fp, (float*)S.r, S.part, &S.np, S.s, S.N));
       KP_TRY(fin(S, 1, FIN_RR_NOCOUNT));
       KP_TRY(launch_cast32_to16(S.ctx, (const float*)S.r, S.x16, S.n3, S.fp16, S.s));
     }
     return precondition_and_update(S, replace ? FIN_PREC_FR : FIN_PREC, true);
   }
-  KP_TRY(launch_stencil_f64(S.ctx, (const double*)S.p, S.c->w64, nullptr, (double*)S.q, S.part, &S.np, S.done, S.N));
+  KP_TRY(launch_stencil_f64(S.ctx, (const double*)S.p, S.c->w64, nullptr, (double*)S.q, S.part, &S.np, S.s, S.N));
   KP_TRY(fin(S, 1, FIN_ALPHA));
   KP_TRY(launch_update_xr<double>(S.ctx, S.x, (const double*)S.p, (double*)S.r, (const double*)S.q,
                                   nullptr, 0, S.s, S.part, &S.np, S.n3));
@@ -177,7 +176,6 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
     S.x16 = (bf16_t*)xv;
   }
   S.s = (Scalars*)sv;
-  S.done = &S.s->done;
   S.part = (double*)pv;
   S.fp = (double*)fpv;
   S.x = x_dev;
@@ -206,6 +204,7 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
     KP_TRY(launch_fill_f64(ctx, x_dev, 0.0, S.n3));
     KP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     KP_HIP(hipStreamSynchronize(ctx->stream));
+    st.status = warn;
     if (stats) *stats = st;
     return warn;
   }
@@ -248,6 +247,7 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
     prev_rr = h.rr;
     if (h.breakdown) {
       st.iters = h.iters;
+      st.status = KP_ERR_BREAKDOWN;
       if (stats) *stats = st;
       return fail(KP_ERR_BREAKDOWN, "pcg_solve: breakdown after %d iterations (pq=%g rho=%g rr=%g)",
                   h.iters, h.pq, h.rho, h.rr);
@@ -300,7 +300,8 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   float ms = 0.f;
   KP_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   st.ms = ms;
+  if (status == KP_OK) status = warn;
+  st.status = status;
   if (stats) *stats = st;
-  if (status == KP_OK) return warn;
   return status;
 }

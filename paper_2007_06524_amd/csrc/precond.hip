@@ -42,6 +42,11 @@ struct OutMap {
   int nd;
 };
 
+// Batch index z = blockIdx.z splits as z = bo * bdiv + bi: the A operand is
+// A + bi * sAb, the B operand B + z * sBb, the output C + bo * sCb at the
+// address map with batch index bi; done[bo * done_stride] != 0 skips the
+// block and out_div[bo * div_stride] scales the results.  (bo is the system
+// of a batched solve, bi the rank term of stage (ii).)
 struct GemmArgs {
   const void* A;   // M x K, row stride lda (16-bit: remainder plane at +a_lo in each row)
   const void* B;   // Nn x K, row stride ldb  (the transposed right operand)
@@ -52,14 +57,19 @@ struct GemmArgs {
   const int* done;
   int vec;                // 1: 16-byte operand loads are legal (alignment and K)
   long long a_lo;         // > 0: A = A[.., k] + A[.., a_lo + k] (hi + lo planes)
-  const double* out_div;  // non-null: results are divided by *out_div
+  const double* out_div;  // non-null: results are divided by out_div[bo * div_stride]
   int order;              // block-to-tile order (tile_of)
+  int bdiv;
+  long long sCb;
+  int done_stride, div_stride;
 };
 
 GemmArgs gemm_args(const void* A, const void* B, void* C, long long M, long long Nn, long long K,
                    long long lda, long long ldb, long long sAb, long long sBb, OutMap om,
-                   const int* done, long long a_lo = 0, const double* out_div = nullptr) {
-  return GemmArgs{A, B, C, (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0, a_lo, out_div, 0};
+                   const int* done, long long a_lo, const double* out_div, int bdiv, long long sCb) {
+  return GemmArgs{A,  B, C,      (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0,
+                  a_lo, out_div, 0, bdiv, sCb, (int)(sizeof(Scalars) / sizeof(int)),
+                  (int)(sizeof(Scalars) / sizeof(double))};
 }
 
 __device__ __forceinline__ long long out_addr(const OutMap& o, int m, int n, int b) {
@@ -117,17 +127,17 @@ __device__ __forceinline__ TO cvt_out(float v) {
 // tile are issued before the MFMAs of the current one.
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
-  if (g.done && *g.done) return;
+  const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
+  if (g.done && g.done[(long long)bo * g.done_stride]) return;
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
   __shared__ double As[BM][BK + 1];
   __shared__ double Bs[BN][BK + 1];
-  const int bz = blockIdx.z;
-  const double* __restrict__ A = (const double*)g.A + (long long)bz * g.sAb;
+  const double* __restrict__ A = (const double*)g.A + (long long)bi * g.sAb;
   const double* __restrict__ B = (const double*)g.B + (long long)bz * g.sBb;
-  double* __restrict__ C = (double*)g.C;
+  double* __restrict__ C = (double*)g.C + (long long)bo * g.sCb;
   int mt, nt;
   tile_of((g.M + BM - 1) / BM, g.order, mt, nt);
   const int m0 = mt * BM, n0 = nt * BN;
@@ -193,7 +203,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm * WM + i * 16 + 4 * v + (lane >> 4);
-        if (m < g.M) C[out_addr(g.om, m, n, bz)] = acc[i][j][v];
+        if (m < g.M) C[out_addr(g.om, m, n, bi)] = acc[i][j][v];
       }
     }
 }
@@ -209,7 +219,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 // fetched into registers while the current one is multiplied.
 template <int BM, int BN, int BK, bool F16, bool SPLIT, typename TO>
 __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
-  if (g.done && *g.done) return;
+  const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
+  if (g.done && g.done[(long long)bo * g.done_stride]) return;
   constexpr bool SWZ = BK == 64;
   constexpr int LDK = SWZ ? BK : BK + 8;
   auto slot = [](int row, int ch) { return SWZ ? ((ch ^ (row & 7)) * 8) : ch * 8; };
@@ -225,10 +236,9 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
   auto As = reinterpret_cast<bf16_t(*)[BM][LDK]>(smem);
   auto Bs = reinterpret_cast<bf16_t(*)[LDK]>(smem + NP * BM * LDK * 2);
-  const int bz = blockIdx.z;
-  const bf16_t* __restrict__ A = (const bf16_t*)g.A + (long long)bz * g.sAb;
+  const bf16_t* __restrict__ A = (const bf16_t*)g.A + (long long)bi * g.sAb;
   const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
-  TO* __restrict__ C = (TO*)g.C;
+  TO* __restrict__ C = (TO*)g.C + (long long)bo * g.sCb;
   int mt, nt;
   tile_of((g.M + BM - 1) / BM, g.order, mt, nt);
   const int m0 = mt * BM, n0 = nt * BN;
@@ -318,7 +328,7 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   // Epilogue: every wave passes its 16 x WN accumulator strips through LDS
   // and writes them as 16-byte vectors along n, which is contiguous in memory
   // whenever sn2 = 1 and the vector stays inside one run of nd columns.
-  const float oscale = g.out_div ? (float)(1.0 / *g.out_div) : 1.0f;
+  const float oscale = g.out_div ? (float)(1.0 / g.out_div[(long long)bo * g.div_stride]) : 1.0f;
   TO* stg = reinterpret_cast<TO*>(smem) + wid * 16 * LDO;
   constexpr int VPR = WN / VL;  // vectors per staged row
   const bool contig = g.om.sn2 == 1;
@@ -337,11 +347,11 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
       const int m = m0 + wm * WM + i * 16 + r, n = n0 + wn * WN + c;
       if (m >= g.M || n >= g.Nn) continue;
       const TO* src = stg + r * LDO + c;
-      TO* dst = C + out_addr(g.om, m, n, bz);
+      TO* dst = C + out_addr(g.om, m, n, bi);
       if (contig && n + VL <= g.Nn && n % g.om.nd + VL <= g.om.nd && ((uintptr_t)dst & 15u) == 0) {
         *(u32x4*)dst = *(const u32x4*)src;
       } else {
-        for (int q = 0; q < VL && n + q < g.Nn; ++q) C[out_addr(g.om, m, n + q, bz)] = src[q];
+        for (int q = 0; q < VL && n + q < g.Nn; ++q) C[out_addr(g.om, m, n + q, bi)] = src[q];
       }
     }
     __syncthreads();
@@ -420,102 +430,112 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
   return KP_OK;
 }
 
-// The three stages.  `planes` = 2 when each circulant row holds (hi | lo).
+// The three stages for a batch of nsys systems.  `planes` = 2 when each
+// circulant row holds (hi | lo).  x: nsys inputs (stride N^3), T and U: nsys
+// intermediates (stride R N^3), z: nsys outputs (stride N^3); s (nullable):
+// per-system done flags and, with `scaled`, the divisors x16_scale.
 struct Stages {
   GemmArgs s1, s2, s3;
+  int nsys, R;
 };
 
 Stages make_stages(int N, int R, const void* x, const void* a1, const void* c2, const void* b3,
-                   void* T, void* U, void* z, const int* done, int planes, const double* out_div) {
+                   void* T, void* U, void* z, int planes, const Scalars* s, bool scaled, int nsys) {
   const long long n = N, nn = n * n, n3 = nn * n, RN = (long long)R * N;
   const long long p = planes;
   const long long lo_n = planes == 2 ? n : 0, lo_rn = planes == 2 ? RN : 0;
-  Stages s;
+  const int* done = s ? &s->done : nullptr;
+  const double* div = (s && scaled) ? &s->x16_scale : nullptr;
+  Stages st;
+  st.nsys = nsys;
+  st.R = R;
   // (i) rows (k,j3), cols (i1,i2), K = i3; addr = m*N^2 + n = T[k][j3][i1][i2].
-  s.s1 = gemm_args(b3, x, T, RN, nn, n, p * n, n, 0, 0, OutMap{nn, 0, 1, 0, INT_MAX}, done, lo_n);
-  // (ii) batch k: rows j2, cols (j3,i1), K = i2; addr = j2*R*N^2 + j3*R*N + k*N + i1.
-  s.s2 = gemm_args(c2, T, U, n, nn, n, p * n, n, p * nn, n3, OutMap{RN * n, RN, 1, n, N}, done, lo_n);
+  st.s1 = gemm_args(b3, x, T, RN, nn, n, p * n, n, 0, n3, OutMap{nn, 0, 1, 0, INT_MAX}, done, lo_n,
+                    nullptr, 1, R * n3);
+  // (ii) batch (system, k): rows j2, cols (j3,i1), K = i2; addr = j2*R*N^2 + j3*R*N + k*N + i1.
+  st.s2 = gemm_args(c2, T, U, n, nn, n, p * n, n, p * nn, n3, OutMap{RN * n, RN, 1, n, N}, done, lo_n,
+                    nullptr, R, R * n3);
   // (iii) rows j1, cols (j2,j3), K = (k,i1); natural row-major output.
-  s.s3 = gemm_args(a1, U, z, n, nn, RN, p * RN, RN, 0, 0, OutMap{nn, 0, 1, 0, INT_MAX}, done, lo_rn,
-                   out_div);
-  return s;
+  st.s3 = gemm_args(a1, U, z, n, nn, RN, p * RN, RN, 0, R * n3, OutMap{nn, 0, 1, 0, INT_MAX}, done,
+                    lo_rn, div, 1, n3);
+  return st;
+}
+
+template <typename F>
+int run_stages(kp_context* ctx, const Stages& st, const int* tiles, F&& run) {
+  {
+    ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE3);
+    KP_TRY(run(0, st.s1, st.nsys, tiles[0]));
+  }
+  {
+    ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE2);
+    KP_TRY(run(1, st.s2, st.nsys * st.R, tiles[1]));
+  }
+  ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE1);
+  return run(2, st.s3, st.nsys, tiles[2]);
 }
 
 }  // namespace
 
 int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, double* z,
-                       const int* done) {
+                       const Scalars* s, const Batch& bt, void* T, void* U, const int* tiles) {
   const size_t n3 = (size_t)pc->N * pc->N * pc->N;
-  void *T, *U;
-  KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(double), &T));
-  KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(double), &U));
-  Stages s = make_stages(pc->N, pc->R, x, pc->a1_64, pc->c2_64, pc->b3_64, T, U, z, done, 1, nullptr);
-  {
-    ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE3);
-    KP_TRY(run_gemm_f64(ctx, s.s1, 1, pc->tile[0]));
-  }
-  {
-    ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE2);
-    KP_TRY(run_gemm_f64(ctx, s.s2, pc->R, pc->tile[1]));
-  }
-  ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE1);
-  KP_TRY(run_gemm_f64(ctx, s.s3, 1, pc->tile[2]));
-  return KP_OK;
+  if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(double), &T));
+  if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(double), &U));
+  Stages st = make_stages(pc->N, pc->R, x, pc->a1_64, pc->c2_64, pc->b3_64, T, U, z, 1, s, false,
+                          bt.nsys);
+  return run_stages(ctx, st, tiles ? tiles : pc->tile,
+                    [&](int, const GemmArgs& g, int batch, int cfg) { return run_gemm_f64(ctx, g, batch, cfg); });
 }
 
 int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, float* z,
-                      const int* done, const double* scale) {
+                      const Scalars* s, const Batch& bt, void* T, void* U, const int* tiles) {
   const size_t n3 = (size_t)pc->N * pc->N * pc->N;
   const bool f16 = pc->precision == KP_MIXED_FP16;
-  void *T, *U;
-  KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(bf16_t), &T));
-  KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(bf16_t), &U));
-  Stages s = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, done, 2, scale);
-  {
-    ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE3);
-    KP_TRY(run_gemm_16<bf16_t>(ctx, s.s1, 1, f16, pc->tile[0]));
-  }
-  {
-    ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE2);
-    KP_TRY(run_gemm_16<bf16_t>(ctx, s.s2, pc->R, f16, pc->tile[1]));
-  }
-  ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE1);
-  KP_TRY(run_gemm_16<float>(ctx, s.s3, 1, f16, pc->tile[2]));
-  return KP_OK;
+  if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(bf16_t), &T));
+  if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(bf16_t), &U));
+  Stages st = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, 2, s, true,
+                          bt.nsys);
+  return run_stages(ctx, st, tiles ? tiles : pc->tile, [&](int stage, const GemmArgs& g, int batch, int cfg) {
+    return stage == 2 ? run_gemm_16<float>(ctx, g, batch, f16, cfg)
+                      : run_gemm_16<bf16_t>(ctx, g, batch, f16, cfg);
+  });
 }
 
 // Times every tile configuration of every stage (`reps` launches each, after
-// one warm-up launch) on the workspace and keeps the fastest per stage.
-int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* table, int cap,
-                     int* count) {
+// one warm-up launch) for a batch of nsys systems and keeps the fastest per
+// stage in tiles[].  Scratch: T, U (nsys R N^3 elements each), X (nsys N^3
+// inputs), Z (nsys N^3 outputs); all NULL: the context workspace (nsys = 1).
+// T, U and X are zero-filled first.
+int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_tile_timing* table,
+                     int cap, int* count, int* tiles, void* T, void* U, void* X, void* Z) {
   const size_t n3 = (size_t)pc->N * pc->N * pc->N;
   const bool sixteen = pc->precision != KP_FP64;
   const size_t el = sixteen ? sizeof(bf16_t) : sizeof(double);
-  void *T, *U, *X, *Z;
-  KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * el, &T));
-  KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * el, &U));
-  KP_TRY(ws_get(ctx, sixteen ? WS_X16 : WS_TMP64, n3 * el, &X));
-  KP_TRY(ws_get(ctx, WS_TMP64B, n3 * sizeof(double), &Z));
-  // Defined operand values (timing does not depend on them).
-  KP_HIP(hipMemsetAsync(T, 0, n3 * pc->R * el, ctx->stream));
-  KP_HIP(hipMemsetAsync(U, 0, n3 * pc->R * el, ctx->stream));
-  KP_HIP(hipMemsetAsync(X, 0, n3 * el, ctx->stream));
-  Stages s = sixteen ? make_stages(pc->N, pc->R, X, pc->a1_16, pc->c2_16, pc->b3_16, T, U, Z, nullptr, 2,
-                                   nullptr)
-                     : make_stages(pc->N, pc->R, X, pc->a1_64, pc->c2_64, pc->b3_64, T, U, Z, nullptr, 1,
-                                   nullptr);
+  if (nsys < 1 || ((!T || !U || !X || !Z) && nsys != 1)) return fail(KP_ERR_ARG, "autotune: bad batch");
+  if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * el, &T));
+  if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * el, &U));
+  if (!X) KP_TRY(ws_get(ctx, sixteen ? WS_X16 : WS_TMP64, n3 * el, &X));
+  if (!Z) KP_TRY(ws_get(ctx, WS_TMP64B, n3 * sizeof(double), &Z));
+  KP_HIP(hipMemsetAsync(T, 0, nsys * n3 * pc->R * el, ctx->stream));
+  KP_HIP(hipMemsetAsync(U, 0, nsys * n3 * pc->R * el, ctx->stream));
+  KP_HIP(hipMemsetAsync(X, 0, nsys * n3 * el, ctx->stream));
+  Stages st = sixteen ? make_stages(pc->N, pc->R, X, pc->a1_16, pc->c2_16, pc->b3_16, T, U, Z, 2,
+                                    nullptr, false, nsys)
+                      : make_stages(pc->N, pc->R, X, pc->a1_64, pc->c2_64, pc->b3_64, T, U, Z, 1,
+                                    nullptr, false, nsys);
   const bool f16 = pc->precision == KP_MIXED_FP16;
   const int ntile = sixteen ? kTiles16 : kTiles64, ncfg = 2 * ntile;
   int n = 0;
-  for (int st = 0; st < 3; ++st) {
-    const GemmArgs& g = st == 0 ? s.s1 : (st == 1 ? s.s2 : s.s3);
-    const int batch = st == 1 ? pc->R : 1;
+  for (int stg = 0; stg < 3; ++stg) {
+    const GemmArgs& g = stg == 0 ? st.s1 : (stg == 1 ? st.s2 : st.s3);
+    const int batch = stg == 1 ? nsys * pc->R : nsys;
     double best = 1e300;
     int best_cfg = -1;
     for (int c = 0; c < ncfg; ++c) {
       auto run = [&]() -> int {
         if (!sixteen) return run_gemm_f64(ctx, g, batch, c);
-        if (st == 2) return run_gemm_16<float>(ctx, g, batch, f16, c);
+        if (stg == 2) return run_gemm_16<float>(ctx, g, batch, f16, c);
         return run_gemm_16<bf16_t>(ctx, g, batch, f16, c);
       };
       KP_TRY(run());
@@ -528,7 +548,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* 
       const double avg = (double)ms / reps;
       if (table && n < cap) {
         kp_tile_timing& e = table[n];
-        e.stage = st;
+        e.stage = stg;
         const int t = c % ntile;
         e.bm = sixteen ? kCfg16[t][0] : kCfg64[t][0];
         e.bn = sixteen ? kCfg16[t][1] : kCfg64[t][1];
@@ -542,7 +562,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* 
         best_cfg = c;
       }
     }
-    pc->tile[st] = best_cfg;
+    tiles[stg] = best_cfg;
   }
   if (count) *count = n;
   return KP_OK;

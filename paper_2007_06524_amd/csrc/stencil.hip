@@ -84,14 +84,21 @@ constexpr int kTY = 4;   // i2 extent of a tile (four wavefronts)
 // neighbours outside the tile (halo, periodic wrap, ragged edges) come from
 // global memory.  MODE 0: out = K u and dot = <u, K u>.  MODE 1: out = f - K u
 // and dot = ||f - K u||^2 (true residual).  Accumulation type C, output type TO.
+// blockIdx.z = system * gz + plane chunk (Batch layout).
 template <typename TU, typename TW, typename TO, typename C, int MODE>
 __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
                                                  const TW* __restrict__ w,
                                                  const double* __restrict__ f,
                                                  TO* __restrict__ out,
                                                  double* __restrict__ partial,
-                                                 const int* __restrict__ done, int N, int TZ) {
-  if (done && *done) return;
+                                                 const Scalars* __restrict__ s, int gate, int N,
+                                                 int TZ, int gz, Batch bt) {
+  const int b = blockIdx.z / gz, zc = blockIdx.z - b * gz;
+  if (s && !gate_open(s[b], gate)) return;
+  u += b * bt.vs;
+  out += b * bt.vs;
+  if (MODE == 1) f += b * bt.vs;
+  w += (size_t)(b / bt.per) * bt.ws;
   __shared__ TU su[kTY][kTX];
   __shared__ TW sw1[kTY][kTX];
   __shared__ TW sw2[kTY][kTX];
@@ -99,7 +106,7 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
   const int ty = threadIdx.x / kTX;
   const int i3 = blockIdx.x * kTX + tx;
   const int i2 = blockIdx.y * kTY + ty;
-  const int z0 = blockIdx.z * TZ;
+  const int z0 = zc * TZ;
   const int z1 = min(z0 + TZ, N);
   const bool act = (i3 < N) && (i2 < N);
   const size_t NN = (size_t)N * N;
@@ -159,25 +166,28 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
     uc = un;
     w0m = w0c;
   }
-  block_sum_store(dot, partial + (blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z)));
+  const size_t nparts = (size_t)gridDim.x * gridDim.y * gz;
+  block_sum_store(dot, partial + b * nparts +
+                           (blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * zc)));
 }
 
 template <typename TU, typename TW, typename TO, typename C, int MODE>
 int run_stencil(kp_context* ctx, const TU* u, const TW* w, const double* f, TO* out,
-                double* partial, int* nparts, const int* done, int N) {
+                double* partial, int* nparts, const Scalars* s, int gate, int N, const Batch& bt) {
   ScopedTimer tm(ctx, MODE == 1 ? KP_TIMER_RESIDUAL : KP_TIMER_STENCIL);
   const int gx = (N + kTX - 1) / kTX;
   const int gy = (N + kTY - 1) / kTY;
   // Enough planes per block to amortize the register queue, enough blocks to fill 256 CUs.
   int TZ = 32;
-  while (TZ > 4 && (size_t)gx * gy * ((N + TZ - 1) / TZ) < 2048) TZ /= 2;
+  while (TZ > 4 && (size_t)gx * gy * ((N + TZ - 1) / TZ) * bt.nsys < 2048) TZ /= 2;
   int gz = (N + TZ - 1) / TZ;
-  while ((size_t)gx * gy * gz > (size_t)kMaxPartials) {
+  while ((size_t)gx * gy * gz > (size_t)kMaxPartials || (size_t)gz * bt.nsys > 65535) {
+    if (TZ >= N) return fail(KP_ERR_ARG, "stencil: batch of %d systems of N=%d too large", bt.nsys, N);
     TZ *= 2;
     gz = (N + TZ - 1) / TZ;
   }
-  hipLaunchKernelGGL((k_stencil<TU, TW, TO, C, MODE>), dim3(gx, gy, gz), dim3(256), 0, ctx->stream,
-                     u, w, f, out, partial, done, N, TZ);
+  hipLaunchKernelGGL((k_stencil<TU, TW, TO, C, MODE>), dim3(gx, gy, gz * bt.nsys), dim3(256), 0,
+                     ctx->stream, u, w, f, out, partial, s, gate, N, TZ, gz, bt);
   KP_HIP(hipGetLastError());
   *nparts = gx * gy * gz;
   return KP_OK;
@@ -213,20 +223,31 @@ int launch_assemble(kp_context* ctx, kp_coeff* c) {
   return KP_OK;
 }
 
+int stencil_parts_max(int N) {
+  return ((N + kTX - 1) / kTX) * ((N + kTY - 1) / kTY) * ((N + 3) / 4);
+}
+
 int launch_stencil_f64(kp_context* ctx, const double* p, const double* w, const double* f,
-                       double* out, double* partial, int* nparts, const int* done, int N) {
-  if (f) return run_stencil<double, double, double, double, 1>(ctx, p, w, f, out, partial, nparts, done, N);
-  return run_stencil<double, double, double, double, 0>(ctx, p, w, nullptr, out, partial, nparts, done, N);
+                       double* out, double* partial, int* nparts, const Scalars* s, int N,
+                       const Batch& bt, int gate) {
+  if (f)
+    return run_stencil<double, double, double, double, 1>(ctx, p, w, f, out, partial, nparts, s, gate,
+                                                          N, bt);
+  return run_stencil<double, double, double, double, 0>(ctx, p, w, nullptr, out, partial, nparts, s,
+                                                        gate, N, bt);
 }
 
 int launch_stencil_f32(kp_context* ctx, const float* p, const float* w, float* out,
-                       double* partial, int* nparts, const int* done, int N) {
-  return run_stencil<float, float, float, float, 0>(ctx, p, w, nullptr, out, partial, nparts, done, N);
+                       double* partial, int* nparts, const Scalars* s, int N, const Batch& bt) {
+  return run_stencil<float, float, float, float, 0>(ctx, p, w, nullptr, out, partial, nparts, s,
+                                                    GATE_ACTIVE, N, bt);
 }
 
 int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* w, const double* f,
-                            float* out, double* partial, int* nparts, const int* done, int N) {
-  return run_stencil<double, double, float, double, 1>(ctx, x, w, f, out, partial, nparts, done, N);
+                            float* out, double* partial, int* nparts, const Scalars* s, int N,
+                            const Batch& bt, int gate) {
+  return run_stencil<double, double, float, double, 1>(ctx, x, w, f, out, partial, nparts, s, gate, N,
+                                                       bt);
 }
 
 }  // namespace kp
