@@ -12,7 +12,9 @@ the timed region.  The cell array is resident on the GPU before timing starts.
 
 Prints one JSON line (metric solves/s: 3 solves per step).  The same
 realization is also solved once in plain FP64 for the mixed-vs-FP64
-comparison, and the CPU oracle is timed on a bounded sample of it.
+comparison, and the CPU oracle is timed on a bounded sample of it.  A
+separate "batched" entry times the batched form (96 realizations of uneven L,
+288 systems) in mixed precision against plain FP64 PCG on the same systems.
 """
 
 from __future__ import annotations
@@ -46,6 +48,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true", help="use the size heuristic for GEMM tiles")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched section (96 realizations of uneven L)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched section and print its JSON (a profiling aid)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain elementwise copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -123,6 +129,64 @@ def cpu_baseline(cells, n0, iters):
     }
 
 
+def batched_section(kp, ctx, eps, reps=2):
+    """The batched form on 96 log-normal realizations with L cycling over {8, 12, 16, 24}
+    (n0 = 4, N = 32..96), three correctors each (288 systems): mixed BF16 batched solves
+    timed over `reps` repetitions after a warm-up (which also tunes the batch tiles),
+    against plain FP64 PCG on the same systems one solve at a time."""
+    import numpy as np
+    import torch
+
+    from workloads import batched_realizations
+
+    cells = batched_realizations(96, sizes=(8, 12, 16, 24), sigma=1.0, seed=4)
+    out = {"workload": "96 realizations, L in {8,12,16,24} (N 32..96), a = exp(N(0,1)), 3 correctors each, "
+                       "tol 1e-8"}
+    res = {}
+    for prec in ("mixed_bf16", "fp64"):
+        coeffs = [kp.Coeff(ctx, c, 4, prec) for c in cells]
+        pcs = {}
+        for co in coeffs:
+            if co.N not in pcs:
+                pcs[co.N] = kp.Precond(ctx, co.N, eps, 0, prec)
+        plist = [pcs[co.N] for co in coeffs]
+        xs = [torch.empty((co.N,) * 3, dtype=torch.float64, device="cuda") for co in coeffs for _ in range(3)]
+        kp.solve_batched(ctx, coeffs, plist, xs=xs, tol=1e-8)          # warm-up + batch tile tuning
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            xs, stats, A, status = kp.solve_batched(ctx, coeffs, plist, xs=xs, tol=1e-8)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        rec = {"batched_s": tb, "systems_per_s": 3 * len(cells) / tb, "status": status,
+               "iters_total": int(sum(s["iters"] for s in stats)),
+               "iters_max": int(max(s["iters"] for s in stats)),
+               "max_relres_true": max(s["relres_true"] for s in stats),
+               "unknown_iters_per_s": sum(s["iters"] * co.N ** 3 for co, s in
+                                          zip([c for c in coeffs for _ in range(3)], stats)) / tb}
+        if prec == "fp64":
+            # the plain solver, one system at a time
+            for pc in pcs.values():
+                pc.autotune(reps=2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for co, pc in zip(coeffs, plist):
+                for i in (1, 2, 3):
+                    kp.solve(ctx, co, pc, rhs=i, tol=1e-8)
+            torch.cuda.synchronize()
+            rec["sequential_s"] = time.perf_counter() - t0
+            rec["sequential_systems_per_s"] = 3 * len(cells) / rec["sequential_s"]
+        res[prec] = (rec, A)
+        for o in coeffs + list(pcs.values()):
+            o.free()
+    out["mixed_bf16"], A_m = res["mixed_bf16"]
+    out["fp64"], A_d = res["fp64"]
+    out["mixed_batched_vs_fp64_plain_time_to_tol"] = out["fp64"]["sequential_s"] / out["mixed_bf16"]["batched_s"]
+    out["mixed_batched_vs_fp64_batched"] = out["fp64"]["batched_s"] / out["mixed_bf16"]["batched_s"]
+    out["mixed_vs_fp64_ahom_max_relerr"] = float(np.max(np.abs(A_m - A_d)) / np.max(np.abs(A_d)))
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -134,6 +198,13 @@ def main():
 
     import paper_2007_06524_amd as kp
     from workloads import CONFIGS, config_cells
+
+    if args.batched_only:
+        ctx = kp.Context(0)
+        out = batched_section(kp, ctx, args.eps, reps=args.steps)
+        ctx.close()
+        print(json.dumps(out))
+        return
 
     if args.copy_probe_mib > 0:
         # One elementwise kernel that reads and writes exactly copy_probe_mib MiB each:
@@ -250,10 +321,17 @@ def main():
         co64.free()
         pc64.free()
 
+    if not args.no_batched:
+        co.free()
+        pc.free()
+        co = pc = None
+        result["batched"] = batched_section(kp, ctx, args.eps)
+
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cells, n0, args.cpu_iters)
-    co.free()
-    pc.free()
+    if co is not None:
+        co.free()
+        pc.free()
     ctx.close()
     print(json.dumps(result))
 
