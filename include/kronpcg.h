@@ -207,13 +207,13 @@ int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors
  * scratch operands of the preconditioner's size) and keeps the fastest per
  * stage for later applies.  table (host, may be NULL) receives up to cap
  * entries {stage 0..2 (contracting i3, i2, (k,i1)), tile rows, tile columns,
- * K tile, block order, average ms}; *count the number of configurations
- * timed.  Block order 0 walks the column tiles of the data operand fastest;
- * order 1 gives all row tiles of one column tile to blocks on the same XCD
- * (one L2), so that column tile is read from HBM once.  Synchronizes the
- * stream. */
+ * K tile, block order, prefetch depth in K tiles, average ms}; *count the
+ * number of configurations timed.  Block order 0 walks the column tiles of
+ * the data operand fastest; order 1 gives all row tiles of one column tile to
+ * blocks on the same XCD (one L2), so that column tile is read from HBM once.
+ * Synchronizes the stream. */
 typedef struct {
-  int stage, bm, bn, bk, order;
+  int stage, bm, bn, bk, order, depth;
   double ms;
 } kp_tile_timing;
 int kp_precond_autotune(kp_context* ctx, kp_precond* pc, int reps, kp_tile_timing* table, int cap,
@@ -263,7 +263,8 @@ int pcg_solve(kp_context* ctx, const kp_coeff* coeff, const kp_precond* pc, int 
  * (j = 0..2) solves corrector j+1 of instance i into x_dev[3 i + j] (device,
  * N_i^3 doubles, caller-owned; read as the initial guess when opts->use_x0,
  * always overwritten with the zero-mean solution).
- * Instances that share a preconditioner form one group; every PCG step of a
+ * Instances that share a preconditioner and the cell size n0 form a group;
+ * every PCG step of a
  * group runs as one launch over all its systems, the groups run as
  * concurrent branches of one HIP graph that holds opts->check_every
  * iterations (0: 16), and the graph is replayed until every system has

@@ -2,13 +2,13 @@
 // three corrector problems of each (eq. DD_Eqn with the right-hand sides of
 // eq. FEM_discr_RHS), as in the Monte-Carlo averages of Section 5.
 //
-// Instances that share a preconditioner (hence one grid size N) form a group.
-// A group's vectors are stored system after system (stride N^3) and its
-// realizations' edge weights realization after realization (stride 3 N^3), so
-// every PCG step of the group is one launch over all its systems (Batch
-// layout).  The PCG control of each system lives in its own device scalars:
+// Instances that share a preconditioner (hence one grid size N) and the cell
+// size n0 form a group.  A group's vectors are stored system after system
+// (stride N^3) and its realizations' cell values realization after
+// realization (stride L^3), so every PCG step of the group is one launch over
+// all its systems (Batch layout).  The PCG control of each system lives in its own device scalars:
 // the recursive residual only requests a true residual (in double, from the
-// double weights), which then decides convergence, the iteration limit, or a
+// double cell values), which then decides convergence, the iteration limit, or a
 // residual replacement (FIN_RR_CTL, FIN_TRUE_CTL).  Stopped systems are masked:
 // every block of theirs returns at once.
 //
@@ -32,7 +32,7 @@ namespace {
 
 struct Group {
   const kp_precond* pc = nullptr;
-  int N = 0;
+  int N = 0, L = 0, n0 = 0;
   size_t n3 = 0;
   std::vector<int> inst;  // instance indices
   int nsys = 0;
@@ -40,8 +40,8 @@ struct Group {
   // device buffers (context allocator)
   double* x = nullptr;    // nsys N^3
   double* fp = nullptr;   // nsys N^3, projected right-hand sides
-  double* w64 = nullptr;  // ninst 3 N^3
-  float* w32 = nullptr;   // ninst 3 N^3 (mixed)
+  double* c64 = nullptr;  // ninst L^3 cell values
+  float* c32 = nullptr;   // ninst L^3 (mixed)
   void *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   bf16_t* x16 = nullptr;
   void *T = nullptr, *U = nullptr;
@@ -103,22 +103,25 @@ int precondition_and_update(kp_context* ctx, BatchState& B, Group& g, int fin_mo
 int true_residual(kp_context* ctx, BatchState& B, Group& g, int gate, int fin_mode) {
   int np = 0;
   if (B.mixed)
-    KP_TRY(launch_resid_f64_to_f32(ctx, g.x, g.w64, g.fp, (float*)g.r, g.part, &np, g.s, g.N, g.bt, gate));
+    KP_TRY(launch_resid_f64_to_f32(ctx, g.x, g.c64, g.L, g.n0, g.fp, (float*)g.r, g.part, &np, g.s, g.N,
+                                   g.bt, gate));
   else
-    KP_TRY(launch_stencil_f64(ctx, g.x, g.w64, g.fp, (double*)g.r, g.part, &np, g.s, g.N, g.bt, gate));
+    KP_TRY(launch_stencil_f64(ctx, g.x, g.c64, g.L, g.n0, g.fp, (double*)g.r, g.part, &np, g.s, g.N, g.bt,
+                              gate));
   return fin(ctx, g, np, 1, fin_mode);
 }
 
 int iteration(kp_context* ctx, BatchState& B, Group& g) {
   int np = 0;
   if (B.mixed) {
-    KP_TRY(launch_stencil_f32(ctx, (const float*)g.p, g.w32, (float*)g.q, g.part, &np, g.s, g.N, g.bt));
+    KP_TRY(launch_stencil_f32(ctx, (const float*)g.p, g.c32, g.L, g.n0, (float*)g.q, g.part, &np, g.s, g.N,
+                              g.bt));
     KP_TRY(fin(ctx, g, np, 1, FIN_ALPHA));
     KP_TRY(launch_update_xr<float>(ctx, g.x, (const float*)g.p, (float*)g.r, (const float*)g.q, g.x16,
                                    B.fp16, g.s, g.part, &np, g.n3, g.bt));
   } else {
-    KP_TRY(launch_stencil_f64(ctx, (const double*)g.p, g.w64, nullptr, (double*)g.q, g.part, &np, g.s,
-                              g.N, g.bt));
+    KP_TRY(launch_stencil_f64(ctx, (const double*)g.p, g.c64, g.L, g.n0, nullptr, (double*)g.q, g.part, &np,
+                              g.s, g.N, g.bt));
     KP_TRY(fin(ctx, g, np, 1, FIN_ALPHA));
     KP_TRY(launch_update_xr<double>(ctx, g.x, (const double*)g.p, (double*)g.r, (const double*)g.q,
                                     nullptr, 0, g.s, g.part, &np, g.n3, g.bt));
@@ -213,13 +216,16 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
   B.mixed = mixed;
   B.fp16 = preconds[0]->precision == KP_MIXED_FP16;
   {
-    std::map<const kp_precond*, int> gid;
+    std::map<std::pair<const kp_precond*, int>, int> gid;
     for (int i = 0; i < n_inst; ++i) {
-      auto it = gid.find(preconds[i]);
+      const auto key = std::make_pair(preconds[i], coeffs[i]->n0);
+      auto it = gid.find(key);
       if (it == gid.end()) {
-        it = gid.emplace(preconds[i], (int)B.groups.size()).first;
+        it = gid.emplace(key, (int)B.groups.size()).first;
         B.groups.emplace_back();
         B.groups.back().pc = preconds[i];
+        B.groups.back().n0 = coeffs[i]->n0;
+        B.groups.back().L = coeffs[i]->L;
       }
       B.groups[it->second].inst.push_back(i);
     }
@@ -235,16 +241,17 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
     g.bt.nsys = g.nsys;
     g.bt.per = 3;
     g.bt.vs = g.n3;
-    g.bt.ws = 3 * g.n3;
+    const size_t nc = (size_t)g.L * g.L * g.L;
+    g.bt.ws = nc;
     total_sys += g.nsys;
     const size_t ns = g.nsys, ni = g.inst.size(), R = g.pc->R;
     const size_t parts = (size_t)8 * std::max(stencil_parts_max(g.N), vector_parts(g.n3));
     void* v;
     KP_TRY(B.alloc(&v, ns * g.n3 * sizeof(double))); g.x = (double*)v;
     KP_TRY(B.alloc(&v, ns * g.n3 * sizeof(double))); g.fp = (double*)v;
-    KP_TRY(B.alloc(&v, ni * 3 * g.n3 * sizeof(double))); g.w64 = (double*)v;
+    KP_TRY(B.alloc(&v, ni * nc * sizeof(double))); g.c64 = (double*)v;
     if (mixed) {
-      KP_TRY(B.alloc(&v, ni * 3 * g.n3 * sizeof(float))); g.w32 = (float*)v;
+      KP_TRY(B.alloc(&v, ni * nc * sizeof(float))); g.c32 = (float*)v;
       KP_TRY(B.alloc(&v, ns * g.n3 * sizeof(bf16_t))); g.x16 = (bf16_t*)v;
     }
     KP_TRY(B.alloc(&g.r, ns * g.n3 * word));
@@ -285,10 +292,11 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
   for (Group& g : B.groups) {
     for (size_t j = 0; j < g.inst.size(); ++j) {
       const kp_coeff* c = coeffs[g.inst[j]];
-      KP_HIP(hipMemcpyAsync(g.w64 + j * 3 * g.n3, c->w64, 3 * g.n3 * sizeof(double), hipMemcpyDeviceToDevice,
+      const size_t nc = (size_t)g.L * g.L * g.L;
+      KP_HIP(hipMemcpyAsync(g.c64 + j * nc, c->cells, nc * sizeof(double), hipMemcpyDeviceToDevice,
                             ctx->stream));
       if (mixed)
-        KP_HIP(hipMemcpyAsync(g.w32 + j * 3 * g.n3, c->w32, 3 * g.n3 * sizeof(float), hipMemcpyDeviceToDevice,
+        KP_HIP(hipMemcpyAsync(g.c32 + j * nc, c->cells32, nc * sizeof(float), hipMemcpyDeviceToDevice,
                               ctx->stream));
       KP_HIP(hipMemcpyAsync(g.fp + j * 3 * g.n3, c->f, 3 * g.n3 * sizeof(double), hipMemcpyDeviceToDevice,
                             ctx->stream));

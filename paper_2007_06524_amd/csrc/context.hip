@@ -407,7 +407,7 @@ int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precis
   if ((st = dev_alloc(ctx, (void**)&c->cells, nc * sizeof(double))) < 0 ||
       (st = dev_alloc(ctx, (void**)&c->w64, 3 * n3 * sizeof(double))) < 0 ||
       (st = dev_alloc(ctx, (void**)&c->f, 3 * n3 * sizeof(double))) < 0 ||
-      (precision != KP_FP64 && (st = dev_alloc(ctx, (void**)&c->w32, 3 * n3 * sizeof(float))) < 0)) {
+      (precision != KP_FP64 && (st = dev_alloc(ctx, (void**)&c->cells32, nc * sizeof(float))) < 0)) {
     kp_free_coeff(c);
     return st;
   }
@@ -441,7 +441,7 @@ int kp_free_coeff(kp_coeff* c) {
   (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx, c->cells);
   dev_free(ctx, c->w64);
-  dev_free(ctx, c->w32);
+  dev_free(ctx, c->cells32);
   dev_free(ctx, c->f);
   delete c;
   return KP_OK;
@@ -451,20 +451,22 @@ int kp_stiffness_apply(kp_context* ctx, const kp_coeff* c, int precision, const 
                        double* q_dev) {
   if (!ctx || !c || !p_dev || !q_dev) return fail(KP_ERR_ARG, "kp_stiffness_apply: NULL argument");
   if (!valid_precision(precision)) return fail(KP_ERR_ARG, "kp_stiffness_apply: bad precision");
-  if (precision != KP_FP64 && !c->w32)
-    return fail(KP_ERR_STATE, "kp_stiffness_apply: coefficient was assembled without float weights");
+  if (precision != KP_FP64 && !c->cells32)
+    return fail(KP_ERR_STATE, "kp_stiffness_apply: coefficient was set up without float cells");
   const int N = c->N;
   const size_t n3 = (size_t)N * N * N;
   void* part;
   KP_TRY(ws_get(ctx, WS_PART, (size_t)kMaxPartials * 8 * sizeof(double), &part));
   int np = 0;
   if (precision == KP_FP64)
-    return launch_stencil_f64(ctx, p_dev, c->w64, nullptr, q_dev, (double*)part, &np, nullptr, N);
+    return launch_stencil_f64(ctx, p_dev, c->cells, c->L, c->n0, nullptr, q_dev, (double*)part, &np,
+                              nullptr, N);
   void *p32, *q32;
   KP_TRY(ws_get(ctx, WS_R, n3 * sizeof(float), &p32));
   KP_TRY(ws_get(ctx, WS_Q, n3 * sizeof(float), &q32));
   KP_TRY(launch_cast_f64_f32(ctx, p_dev, (float*)p32, n3));
-  KP_TRY(launch_stencil_f32(ctx, (const float*)p32, c->w32, (float*)q32, (double*)part, &np, nullptr, N));
+  KP_TRY(launch_stencil_f32(ctx, (const float*)p32, c->cells32, c->L, c->n0, (float*)q32, (double*)part,
+                            &np, nullptr, N));
   return launch_cast_f32_f64(ctx, (const float*)q32, q_dev, n3);
 }
 

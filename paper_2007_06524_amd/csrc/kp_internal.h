@@ -162,10 +162,10 @@ struct kp_coeff {
   kp_context* ctx = nullptr;
   int L = 0, n0 = 0, N = 0;
   int precision = KP_FP64;
-  double* cells = nullptr;  // L^3
-  double* w64 = nullptr;    // 3 N^3
-  float* w32 = nullptr;     // 3 N^3 (mixed only)
-  double* f = nullptr;      // 3 N^3
+  double* cells = nullptr;   // L^3 (the stencils read the coefficient from here)
+  float* cells32 = nullptr;  // L^3 float copy (mixed only)
+  double* w64 = nullptr;     // 3 N^3 assembled edge weights (kp_coeff_fields)
+  double* f = nullptr;       // 3 N^3
 };
 
 struct kp_precond {
@@ -213,17 +213,19 @@ int launch_assemble(kp_context* ctx, kp_coeff* c);
 // Sets *bad (device int, zeroed by the caller) when a cell is not finite or <= 0.
 int launch_validate_cells(kp_context* ctx, const double* cells, size_t n, int* bad);
 
-// Stencil q = K p (or out = f - K p when f is given), block partials of <p,q>
-// (or ||out||^2).  s (nullable) gates the systems (gate: enum Gate).
-int launch_stencil_f64(kp_context* ctx, const double* p, const double* w, const double* f,
-                       double* out, double* partial, int* nparts, const Scalars* s, int N,
-                       const Batch& bt = Batch(), int gate = GATE_ACTIVE);
-int launch_stencil_f32(kp_context* ctx, const float* p, const float* w, float* out,
+// Stencil q = K p (or out = f - K p when f is given) on the coefficient given
+// by its L^3 cells (n0 grid intervals per cell), block partials of <p,q> (or
+// ||out||^2).  s (nullable) gates the systems (gate: enum Gate); bt.ws strides
+// the cells of successive realizations.
+int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, int L, int n0,
+                       const double* f, double* out, double* partial, int* nparts, const Scalars* s,
+                       int N, const Batch& bt = Batch(), int gate = GATE_ACTIVE);
+int launch_stencil_f32(kp_context* ctx, const float* p, const float* cells, int L, int n0, float* out,
                        double* partial, int* nparts, const Scalars* s, int N,
                        const Batch& bt = Batch());
-int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* w, const double* f,
-                            float* out, double* partial, int* nparts, const Scalars* s, int N,
-                            const Batch& bt = Batch(), int gate = GATE_ACTIVE);
+int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* cells, int L, int n0,
+                            const double* f, float* out, double* partial, int* nparts,
+                            const Scalars* s, int N, const Batch& bt = Batch(), int gate = GATE_ACTIVE);
 
 // One block per system: totals of nvals values, then the scalar update `mode`.
 int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nvals, int mode,

@@ -22,6 +22,7 @@
 // 16-bit rounding of the dense circulant entries resolves.
 
 #include <climits>
+#include <type_traits>
 
 #include "kp_internal.h"
 
@@ -125,7 +126,8 @@ __device__ __forceinline__ TO cvt_out(float v) {
 // 256 threads = 2 x 2 wavefronts, block tile BM x BN, K tile 16, wave tile
 // (BM/2) x (BN/2) made of 16 x 16 MFMA tiles.  Global loads for the next K
 // tile are issued before the MFMAs of the current one.
-template <int BM, int BN>
+// STAGE (0..2) only separates the three stages' kernel names in profiles.
+template <int STAGE, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
   if (g.done && g.done[(long long)bo * g.done_stride]) return;
@@ -209,21 +211,29 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 }
 
 // ---------------------------------------------------- BF16 / FP16 MFMA
+// LDS barrier that leaves global loads in flight: waits for this wave's LDS
+// accesses only (a __syncthreads would also wait for the register prefetch).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
 // 256 threads = 2 x 2 wavefronts, block tile BM x BN, K tile BK (BK/32
 // 16x16x32 steps).  Operands move as 16-byte vectors of eight 16-bit values.
-// LDS: with BK = 64 a row is 128 bytes = eight 16-byte chunks and chunk c of
-// row r is stored at slot c ^ (r & 7) (no padding), so that the eight rows
-// read by one fragment load hit eight different chunk slots; with BK = 32
-// rows are padded by 16 bytes.  With SPLIT the A tile is staged twice (hi
-// and lo planes) and every B fragment feeds two MFMAs.  The next K tile is
-// fetched into registers while the current one is multiplied.
-template <int BM, int BN, int BK, bool F16, bool SPLIT, typename TO>
+// LDS rows hold BK values as 16-byte chunks, chunk c of row r at slot
+// c ^ (r & 7) (BK = 64, eight chunks) or c ^ ((r >> 2) & 3) (BK = 32, four
+// chunks), so that the rows one fragment load touches fall in different
+// banks; no padding.  With SPLIT the A tile is staged twice (hi and lo
+// planes) and every B fragment feeds two MFMAs.  The K tiles are fetched PF
+// tiles ahead into registers (a ring of PF register sets), so a load has PF
+// steps of MFMAs to arrive.
+template <int STAGE, int BM, int BN, int BK, int PF, bool F16, bool SPLIT, typename TO>
 __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
   if (g.done && g.done[(long long)bo * g.done_stride]) return;
-  constexpr bool SWZ = BK == 64;
-  constexpr int LDK = SWZ ? BK : BK + 8;
-  auto slot = [](int row, int ch) { return SWZ ? ((ch ^ (row & 7)) * 8) : ch * 8; };
+  static_assert(BK == 32 || BK == 64, "K tile");
+  constexpr int CH = BK / 8;  // 16-byte chunks per row
+  auto slot = [](int row, int ch) { return (CH == 8 ? (ch ^ (row & 7)) : (ch ^ ((row >> 2) & 3))) * 8; };
   constexpr int NP = SPLIT ? 2 : 1;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -231,11 +241,11 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   // Operand tiles; after the K loop the same memory stages the output.
   constexpr int VL = 16 / (int)sizeof(TO);  // output elements per 16-byte vector
   constexpr int LDO = WN + VL;              // padded staging row of one wave
-  constexpr int OP_BYTES = (NP * BM + BN) * LDK * 2;
+  constexpr int OP_BYTES = (NP * BM + BN) * BK * 2;
   constexpr int STG_BYTES = 4 * 16 * LDO * (int)sizeof(TO);
   __shared__ __attribute__((aligned(16))) unsigned char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
-  auto As = reinterpret_cast<bf16_t(*)[BM][LDK]>(smem);
-  auto Bs = reinterpret_cast<bf16_t(*)[LDK]>(smem + NP * BM * LDK * 2);
+  auto As = reinterpret_cast<bf16_t(*)[BM][BK]>(smem);
+  auto Bs = reinterpret_cast<bf16_t(*)[BK]>(smem + NP * BM * BK * 2);
   const bf16_t* __restrict__ A = (const bf16_t*)g.A + (long long)bi * g.sAb;
   const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
   TO* __restrict__ C = (TO*)g.C + (long long)bo * g.sCb;
@@ -250,10 +260,10 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  u32x4 ra[NP][VA], rb[VB];
+  u32x4 ra[PF][NP][VA], rb[PF][VB];
   auto load_vec = [&](const bf16_t* __restrict__ P, long long ld, int rows, int r0, int k0, int e,
                       u32x4& dst) {
-    const int r = e / (BK / 8), c = (e % (BK / 8)) * 8;
+    const int r = e / CH, c = (e % CH) * 8;
     const int gr = r0 + r, gk = k0 + c;
     if (gr < rows && g.vec && gk + 8 <= g.K) {
       dst = *(const u32x4*)(P + (long long)gr * ld + gk);
@@ -268,13 +278,14 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
       dst = u32x4{w[0], w[1], w[2], w[3]};
     }
   };
-  auto load = [&](int k0) {
+  auto load = [&](int k0, auto sc) {
+    constexpr int S = decltype(sc)::value;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int t = 0; t < VA; ++t) load_vec(A + p * g.a_lo, g.lda, g.M, m0, k0, tid + 256 * t, ra[p][t]);
+      for (int t = 0; t < VA; ++t) load_vec(A + p * g.a_lo, g.lda, g.M, m0, k0, tid + 256 * t, ra[S][p][t]);
 #pragma unroll
-    for (int t = 0; t < VB; ++t) load_vec(B, g.ldb, g.Nn, n0, k0, tid + 256 * t, rb[t]);
+    for (int t = 0; t < VB; ++t) load_vec(B, g.ldb, g.Nn, n0, k0, tid + 256 * t, rb[S][t]);
   };
   auto mfma = [&](const u32x4& a, const u32x4& b, flt4& c) {
     if constexpr (F16)
@@ -284,22 +295,24 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   };
-  load(0);
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
+  // One K tile: registers of ring slot S -> LDS, refill the slot PF tiles
+  // ahead, multiply.
+  auto step = [&](int k0, auto sc) {
+    constexpr int S = decltype(sc)::value;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int t = 0; t < VA; ++t) {
-        const int e = tid + 256 * t, row = e / (BK / 8);
-        *(u32x4*)&As[p][row][slot(row, e % (BK / 8))] = ra[p][t];
+        const int e = tid + 256 * t, row = e / CH;
+        *(u32x4*)&As[p][row][slot(row, e % CH)] = ra[S][p][t];
       }
 #pragma unroll
     for (int t = 0; t < VB; ++t) {
-      const int e = tid + 256 * t, row = e / (BK / 8);
-      *(u32x4*)&Bs[row][slot(row, e % (BK / 8))] = rb[t];
+      const int e = tid + 256 * t, row = e / CH;
+      *(u32x4*)&Bs[row][slot(row, e % CH)] = rb[S][t];
     }
-    __syncthreads();
-    if (k0 + BK < g.K) load(k0 + BK);
+    lds_barrier();
+    if (k0 + PF * BK < g.K) load(k0 + PF * BK, sc);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 32) {
       const int ch = ks / 8 + (lane >> 4);
@@ -323,8 +336,19 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
           for (int j = 0; j < TN; ++j) mfma(af[i], bfr[j], acc[i][j]);
       }
     }
-    __syncthreads();
+    lds_barrier();
+  };
+  load(0, IC<0>());
+  if constexpr (PF == 2) {
+    if (BK < g.K) load(BK, IC<1>());
+    for (int k0 = 0; k0 < g.K; k0 += 2 * BK) {
+      step(k0, IC<0>());
+      if (k0 + BK < g.K) step(k0 + BK, IC<1>());
+    }
+  } else {
+    for (int k0 = 0; k0 < g.K; k0 += BK) step(k0, IC<0>());
   }
+  __syncthreads();
   // Epilogue: every wave passes its 16 x WN accumulator strips through LDS
   // and writes them as 16-byte vectors along n, which is contiguous in memory
   // whenever sn2 = 1 and the vector stays inside one run of nd columns.
@@ -363,68 +387,73 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // Tile configurations (block rows x block columns [x K tile for 16-bit]).  The
 // autotuner times them per stage; without tuning a size heuristic picks one.
 constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-constexpr int kCfg16[kTiles16][3] = {{64, 64, 64},   {128, 64, 64},  {64, 128, 64},
-                                     {128, 128, 64}, {128, 128, 32}, {256, 128, 64},
-                                     {256, 128, 32}, {128, 256, 32}};
+// 16-bit: {BM, BN, BK, prefetch depth}.
+constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 1},   {128, 64, 64, 1},  {64, 128, 64, 1},
+                                     {128, 128, 64, 1}, {128, 128, 32, 1}, {64, 128, 32, 2},
+                                     {128, 128, 32, 2}, {64, 128, 64, 2}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
 }
 
+// Large problems: 64 x 128 x 64 in the XCD-grouped order (the fastest on the
+// N = 256 stages when measured); small ones: 64 x 64.
 int heuristic16(const GemmArgs& g, int batch) {
-  if (g.M >= 256 && (long long)g.M * g.Nn * batch >= 256LL * 128 * 512) return 5;
-  if (g.M >= 128 && (long long)g.M * g.Nn * batch >= 128LL * 128 * 256) return 3;
+  if ((long long)g.M * g.Nn * batch >= 128LL * 128 * 256) return 2 + kTiles16;
   return 0;
 }
 
 template <int BM, int BN>
-void launch64(kp_context* ctx, const GemmArgs& g, int batch) {
+void launch64(kp_context* ctx, const GemmArgs& g, int batch, int stage) {
   dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
-  hipLaunchKernelGGL((k_gemm_f64<BM, BN>), grid, dim3(256), 0, ctx->stream, g);
+  if (stage == 0) hipLaunchKernelGGL((k_gemm_f64<0, BM, BN>), grid, dim3(256), 0, ctx->stream, g);
+  else if (stage == 1) hipLaunchKernelGGL((k_gemm_f64<1, BM, BN>), grid, dim3(256), 0, ctx->stream, g);
+  else hipLaunchKernelGGL((k_gemm_f64<2, BM, BN>), grid, dim3(256), 0, ctx->stream, g);
 }
 
 // cfg = tile + kTiles64 * order; out of range: size heuristic, order 0.
-int run_gemm_f64(kp_context* ctx, GemmArgs g, int batch, int cfg) {
+int run_gemm_f64(kp_context* ctx, GemmArgs g, int batch, int cfg, int stage) {
   if (cfg < 0 || cfg >= 2 * kTiles64) cfg = heuristic64(g);
   g.order = cfg / kTiles64;
   switch (cfg % kTiles64) {
-    case 0: launch64<64, 64>(ctx, g, batch); break;
-    case 1: launch64<128, 64>(ctx, g, batch); break;
-    case 2: launch64<64, 128>(ctx, g, batch); break;
-    default: launch64<128, 128>(ctx, g, batch); break;
+    case 0: launch64<64, 64>(ctx, g, batch, stage); break;
+    case 1: launch64<128, 64>(ctx, g, batch, stage); break;
+    case 2: launch64<64, 128>(ctx, g, batch, stage); break;
+    default: launch64<128, 128>(ctx, g, batch, stage); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
 }
 
-template <int BM, int BN, int BK, typename TO>
+template <int STAGE, int BM, int BN, int BK, int PF, typename TO>
 void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
   dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
   if (g.a_lo) {
-    if (f16) hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, true, true, TO>), grid, dim3(256), 0, ctx->stream, g);
-    else hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, false, true, TO>), grid, dim3(256), 0, ctx->stream, g);
+    if (f16) hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, true, true, TO>), grid, dim3(256), 0, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, false, true, TO>), grid, dim3(256), 0, ctx->stream, g);
   } else {
-    if (f16) hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, true, false, TO>), grid, dim3(256), 0, ctx->stream, g);
-    else hipLaunchKernelGGL((k_gemm_16<BM, BN, BK, false, false, TO>), grid, dim3(256), 0, ctx->stream, g);
+    if (f16) hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, true, false, TO>), grid, dim3(256), 0, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, false, false, TO>), grid, dim3(256), 0, ctx->stream, g);
   }
 }
 
 // cfg = tile + kTiles16 * order; out of range: size heuristic, order 0.
-template <typename TO>
+// Stages 0 and 1 write 16-bit intermediates, stage 2 the float result.
+template <int STAGE, typename TO>
 int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
   g.vec = (g.K % 8 == 0) && (g.lda % 8 == 0) && (g.ldb % 8 == 0) && (g.sAb % 8 == 0) &&
           (g.sBb % 8 == 0) && (g.a_lo % 8 == 0) && aligned16(g.A) && aligned16(g.B);
   if (cfg < 0 || cfg >= 2 * kTiles16) cfg = heuristic16(g, batch);
   g.order = cfg / kTiles16;
   switch (cfg % kTiles16) {
-    case 0: launch16<64, 64, 64, TO>(ctx, g, batch, f16); break;
-    case 1: launch16<128, 64, 64, TO>(ctx, g, batch, f16); break;
-    case 2: launch16<64, 128, 64, TO>(ctx, g, batch, f16); break;
-    case 3: launch16<128, 128, 64, TO>(ctx, g, batch, f16); break;
-    case 4: launch16<128, 128, 32, TO>(ctx, g, batch, f16); break;
-    case 5: launch16<256, 128, 64, TO>(ctx, g, batch, f16); break;
-    case 6: launch16<256, 128, 32, TO>(ctx, g, batch, f16); break;
-    default: launch16<128, 256, 32, TO>(ctx, g, batch, f16); break;
+    case 0: launch16<STAGE, 64, 64, 64, 1, TO>(ctx, g, batch, f16); break;
+    case 1: launch16<STAGE, 128, 64, 64, 1, TO>(ctx, g, batch, f16); break;
+    case 2: launch16<STAGE, 64, 128, 64, 1, TO>(ctx, g, batch, f16); break;
+    case 3: launch16<STAGE, 128, 128, 64, 1, TO>(ctx, g, batch, f16); break;
+    case 4: launch16<STAGE, 128, 128, 32, 1, TO>(ctx, g, batch, f16); break;
+    case 5: launch16<STAGE, 64, 128, 32, 2, TO>(ctx, g, batch, f16); break;
+    case 6: launch16<STAGE, 128, 128, 32, 2, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 64, 128, 64, 2, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
@@ -485,7 +514,9 @@ int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, d
   Stages st = make_stages(pc->N, pc->R, x, pc->a1_64, pc->c2_64, pc->b3_64, T, U, z, 1, s, false,
                           bt.nsys);
   return run_stages(ctx, st, tiles ? tiles : pc->tile,
-                    [&](int, const GemmArgs& g, int batch, int cfg) { return run_gemm_f64(ctx, g, batch, cfg); });
+                    [&](int stage, const GemmArgs& g, int batch, int cfg) {
+                      return run_gemm_f64(ctx, g, batch, cfg, stage);
+                    });
 }
 
 int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, float* z,
@@ -497,8 +528,9 @@ int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, fl
   Stages st = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, 2, s, true,
                           bt.nsys);
   return run_stages(ctx, st, tiles ? tiles : pc->tile, [&](int stage, const GemmArgs& g, int batch, int cfg) {
-    return stage == 2 ? run_gemm_16<float>(ctx, g, batch, f16, cfg)
-                      : run_gemm_16<bf16_t>(ctx, g, batch, f16, cfg);
+    if (stage == 0) return run_gemm_16<0, bf16_t>(ctx, g, batch, f16, cfg);
+    if (stage == 1) return run_gemm_16<1, bf16_t>(ctx, g, batch, f16, cfg);
+    return run_gemm_16<2, float>(ctx, g, batch, f16, cfg);
   });
 }
 
@@ -534,9 +566,10 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
     int best_cfg = -1;
     for (int c = 0; c < ncfg; ++c) {
       auto run = [&]() -> int {
-        if (!sixteen) return run_gemm_f64(ctx, g, batch, c);
-        if (stg == 2) return run_gemm_16<float>(ctx, g, batch, f16, c);
-        return run_gemm_16<bf16_t>(ctx, g, batch, f16, c);
+        if (!sixteen) return run_gemm_f64(ctx, g, batch, c, stg);
+        if (stg == 0) return run_gemm_16<0, bf16_t>(ctx, g, batch, f16, c);
+        if (stg == 1) return run_gemm_16<1, bf16_t>(ctx, g, batch, f16, c);
+        return run_gemm_16<2, float>(ctx, g, batch, f16, c);
       };
       KP_TRY(run());
       KP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
@@ -553,6 +586,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         e.bm = sixteen ? kCfg16[t][0] : kCfg64[t][0];
         e.bn = sixteen ? kCfg16[t][1] : kCfg64[t][1];
         e.bk = sixteen ? kCfg16[t][2] : 16;
+        e.depth = sixteen ? kCfg16[t][3] : 1;
         e.order = c / ntile;
         e.ms = avg;
       }

@@ -38,7 +38,6 @@ __device__ __forceinline__ void block_sum_store(double v, double* out) {
 // One thread per node; the eight voxels around node p are v = p - 1 + d, d in {0,1}^3.
 __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ cells, int L, int n0,
                                                   int N, double h, double* __restrict__ w64,
-                                                  float* __restrict__ w32,
                                                   double* __restrict__ f) {
   const size_t n3 = (size_t)N * N * N;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,11 +64,6 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ cel
   w64[idx] = w0;
   w64[n3 + idx] = w1;
   w64[2 * n3 + idx] = w2;
-  if (w32) {
-    w32[idx] = (float)w0;
-    w32[n3 + idx] = (float)w1;
-    w32[2 * n3 + idx] = (float)w2;
-  }
   f[idx] = h * (w0 - w0m);
   f[n3 + idx] = h * (w1 - w1m);
   f[2 * n3 + idx] = h * (w2 - w2m);
@@ -78,16 +72,35 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ cel
 constexpr int kTX = 64;  // i3 extent of a tile (one wavefront)
 constexpr int kTY = 4;   // i2 extent of a tile (four wavefronts)
 
-// 2.5D tiled stencil.  A 64 x 4 block of columns (i2, i3) marches along i1 over
-// TZ planes; the i1 neighbours and w_1(p - e_1) ride in registers, the current
-// plane of u and of w_2, w_3 is staged in LDS for the in-plane neighbours, and
-// neighbours outside the tile (halo, periodic wrap, ragged edges) come from
-// global memory.  MODE 0: out = K u and dot = <u, K u>.  MODE 1: out = f - K u
-// and dot = ||f - K u||^2 (true residual).  Accumulation type C, output type TO.
-// blockIdx.z = system * gz + plane chunk (Batch layout).
-template <typename TU, typename TW, typename TO, typename C, int MODE>
-__global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
-                                                 const TW* __restrict__ w,
+// Coefficient of one realization as the stencil reads it: the L^3 cell values
+// [c1][c2][c3] (cell of voxel v: v / n0 per axis).
+template <typename TC>
+struct Cells {
+  const TC* a;
+  int L, n0;
+};
+
+// 2.5D tiled stencil on the cell values.  The edge weights are not read from
+// memory: around node p the eight voxels v = p - 1 + d, d in {0,1}^3, belong to
+// cells a[d1][d2][d3], and each of the six weights of p is the mean of the four
+// voxels on one side (w_1(p) = mean of a[1][.][.], w_1(p - e_1) of a[0][.][.],
+// and so on), summed in the order of the assembly kernel, so that in double
+// the weights are those of k_assemble bit for bit.  Along i1 the layer
+// a[1][.][.] of plane z is the layer a[0][.][.] of plane z + 1 and changes only
+// when z crosses a cell boundary, so a thread loads four cell values once per
+// n0 planes (cache hits: the L^3 cells are 64 times smaller than a field).
+// Traffic: the field u (with its halo) and the output, two words per node.
+//
+// A 64 x 4 block of columns (i2, i3) marches along i1 over TZ planes; the i1
+// neighbours of u ride in registers, the current plane of u is staged in LDS
+// for the in-plane neighbours, and neighbours outside the tile (halo,
+// periodic wrap, ragged edges) come from global memory.  MODE 0: out = K u
+// and dot = <u, K u>.  MODE 1: out = f - K u and dot = ||f - K u||^2 (true
+// residual).  Cell type TC, accumulation type C, output type TO.
+// blockIdx.z = system * gz + plane chunk (Batch layout; bt.ws strides the
+// cells of successive realizations).
+template <typename TU, typename TC, typename TO, typename C, int MODE>
+__global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u, Cells<TC> cc,
                                                  const double* __restrict__ f,
                                                  TO* __restrict__ out,
                                                  double* __restrict__ partial,
@@ -98,10 +111,9 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
   u += b * bt.vs;
   out += b * bt.vs;
   if (MODE == 1) f += b * bt.vs;
-  w += (size_t)(b / bt.per) * bt.ws;
+  const TC* __restrict__ cells = cc.a + (size_t)(b / bt.per) * bt.ws;
+  const int L = cc.L, n0 = cc.n0;
   __shared__ TU su[kTY][kTX];
-  __shared__ TW sw1[kTY][kTX];
-  __shared__ TW sw2[kTY][kTX];
   const int tx = threadIdx.x & (kTX - 1);
   const int ty = threadIdx.x / kTX;
   const int i3 = blockIdx.x * kTX + tx;
@@ -110,35 +122,42 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
   const int z1 = min(z0 + TZ, N);
   const bool act = (i3 < N) && (i2 < N);
   const size_t NN = (size_t)N * N;
-  const size_t n3 = NN * N;
-  const TW* w0 = w;
-  const TW* w1 = w + n3;
-  const TW* w2 = w + 2 * n3;
   const int i2m = (i2 == 0) ? N - 1 : i2 - 1;
   const int i2p = (i2 + 1 >= N) ? 0 : i2 + 1;
   const int i3m = (i3 == 0) ? N - 1 : i3 - 1;
   const int i3p = (i3 + 1 >= N) ? 0 : i3 + 1;
   const size_t col = (size_t)i2 * N + i3;
+  // Transverse cell offsets: [d2][d3] -> c2 * L + c3 for d = 0 (p - 1) and 1 (p).
+  int toff[2][2] = {{0, 0}, {0, 0}};
+  if (act) {
+    const int c2[2] = {i2m / n0, i2 / n0}, c3[2] = {i3m / n0, i3 / n0};
+    for (int d2 = 0; d2 < 2; ++d2)
+      for (int d3 = 0; d3 < 2; ++d3) toff[d2][d3] = c2[d2] * L + c3[d3];
+  }
+  auto layer = [&](int c1, C (&a)[2][2]) {
+    const size_t base = (size_t)c1 * L * L;
+#pragma unroll
+    for (int d2 = 0; d2 < 2; ++d2)
+#pragma unroll
+      for (int d3 = 0; d3 < 2; ++d3) a[d2][d3] = (C)cells[base + toff[d2][d3]];
+  };
   double dot = 0.0;
-  C um = 0, uc = 0, un = 0, w0m = 0;
+  C um = 0, uc = 0, un = 0;
+  C a0[2][2] = {{0, 0}, {0, 0}}, a1[2][2] = {{0, 0}, {0, 0}};
+  int cz = z0 / n0, rz = z0 - cz * n0;  // cell layer of plane z and position inside it
   if (act) {
     const int zm = (z0 == 0) ? N - 1 : z0 - 1;
     um = (C)u[zm * NN + col];
     uc = (C)u[z0 * NN + col];
-    w0m = (C)w0[zm * NN + col];
+    layer(zm / n0, a0);
+    layer(cz, a1);
   }
   for (int z = z0; z < z1; ++z) {
-    C w0c = 0, w1c = 0, w2c = 0;
     const size_t base = (size_t)z * NN;
     if (act) {
       const int zp = (z + 1 >= N) ? 0 : z + 1;
       un = (C)u[zp * NN + col];
-      w0c = (C)w0[base + col];
-      w1c = (C)w1[base + col];
-      w2c = (C)w2[base + col];
       su[ty][tx] = (TU)uc;
-      sw1[ty][tx] = (TW)w1c;
-      sw2[ty][tx] = (TW)w2c;
     }
     __syncthreads();
     if (act) {
@@ -146,8 +165,13 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
       const C u2p = (ty + 1 < kTY && i2 + 1 < N) ? (C)su[ty + 1][tx] : (C)u[base + (size_t)i2p * N + i3];
       const C u3m = (tx > 0) ? (C)su[ty][tx - 1] : (C)u[base + (size_t)i2 * N + i3m];
       const C u3p = (tx + 1 < kTX && i3 + 1 < N) ? (C)su[ty][tx + 1] : (C)u[base + (size_t)i2 * N + i3p];
-      const C w1m = (ty > 0) ? (C)sw1[ty - 1][tx] : (C)w1[base + (size_t)i2m * N + i3];
-      const C w2m = (tx > 0) ? (C)sw2[ty][tx - 1] : (C)w2[base + (size_t)i2 * N + i3m];
+      const C q = (C)0.25;
+      const C w0c = (((a1[1][1] + a1[0][1]) + a1[1][0]) + a1[0][0]) * q;
+      const C w0m = (((a0[1][1] + a0[0][1]) + a0[1][0]) + a0[0][0]) * q;
+      const C w1c = (((a1[1][1] + a0[1][1]) + a1[1][0]) + a0[1][0]) * q;
+      const C w1m = (((a1[0][1] + a0[0][1]) + a1[0][0]) + a0[0][0]) * q;
+      const C w2c = (((a1[1][1] + a0[1][1]) + a1[0][1]) + a0[0][1]) * q;
+      const C w2m = (((a1[1][0] + a0[1][0]) + a1[0][0]) + a0[0][0]) * q;
       C ku = w0c * (uc - un) + w0m * (uc - um);
       ku += w1c * (uc - u2p) + w1m * (uc - u2m);
       ku += w2c * (uc - u3p) + w2m * (uc - u3m);
@@ -160,19 +184,28 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
         out[base + col] = (TO)res;
         dot += res * res;
       }
+      // next plane: layer a1 becomes a0; a new layer when z + 1 starts a cell
+#pragma unroll
+      for (int d2 = 0; d2 < 2; ++d2)
+#pragma unroll
+        for (int d3 = 0; d3 < 2; ++d3) a0[d2][d3] = a1[d2][d3];
+      if (++rz == n0) {
+        rz = 0;
+        ++cz;
+        if (z + 1 < z1) layer(cz, a1);
+      }
     }
     __syncthreads();
     um = uc;
     uc = un;
-    w0m = w0c;
   }
   const size_t nparts = (size_t)gridDim.x * gridDim.y * gz;
   block_sum_store(dot, partial + b * nparts +
                            (blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * zc)));
 }
 
-template <typename TU, typename TW, typename TO, typename C, int MODE>
-int run_stencil(kp_context* ctx, const TU* u, const TW* w, const double* f, TO* out,
+template <typename TU, typename TC, typename TO, typename C, int MODE>
+int run_stencil(kp_context* ctx, const TU* u, Cells<TC> cc, const double* f, TO* out,
                 double* partial, int* nparts, const Scalars* s, int gate, int N, const Batch& bt) {
   ScopedTimer tm(ctx, MODE == 1 ? KP_TIMER_RESIDUAL : KP_TIMER_STENCIL);
   const int gx = (N + kTX - 1) / kTX;
@@ -186,8 +219,8 @@ int run_stencil(kp_context* ctx, const TU* u, const TW* w, const double* f, TO* 
     TZ *= 2;
     gz = (N + TZ - 1) / TZ;
   }
-  hipLaunchKernelGGL((k_stencil<TU, TW, TO, C, MODE>), dim3(gx, gy, gz * bt.nsys), dim3(256), 0,
-                     ctx->stream, u, w, f, out, partial, s, gate, N, TZ, gz, bt);
+  hipLaunchKernelGGL((k_stencil<TU, TC, TO, C, MODE>), dim3(gx, gy, gz * bt.nsys), dim3(256), 0,
+                     ctx->stream, u, cc, f, out, partial, s, gate, N, TZ, gz, bt);
   KP_HIP(hipGetLastError());
   *nparts = gx * gy * gz;
   return KP_OK;
@@ -218,36 +251,39 @@ int launch_assemble(kp_context* ctx, kp_coeff* c) {
   const size_t n3 = (size_t)c->N * c->N * c->N;
   const int blocks = (int)((n3 + 255) / 256);
   hipLaunchKernelGGL(k_assemble, dim3(blocks), dim3(256), 0, ctx->stream, c->cells, c->L, c->n0,
-                     c->N, 1.0 / c->N, c->w64, c->w32, c->f);
+                     c->N, 1.0 / c->N, c->w64, c->f);
   KP_HIP(hipGetLastError());
+  if (c->cells32) return launch_cast_f64_f32(ctx, c->cells, c->cells32, (size_t)c->L * c->L * c->L);
   return KP_OK;
 }
+
 
 int stencil_parts_max(int N) {
   return ((N + kTX - 1) / kTX) * ((N + kTY - 1) / kTY) * ((N + 3) / 4);
 }
 
-int launch_stencil_f64(kp_context* ctx, const double* p, const double* w, const double* f,
-                       double* out, double* partial, int* nparts, const Scalars* s, int N,
-                       const Batch& bt, int gate) {
+int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, int L, int n0,
+                       const double* f, double* out, double* partial, int* nparts, const Scalars* s,
+                       int N, const Batch& bt, int gate) {
+  const Cells<double> cc{cells, L, n0};
   if (f)
-    return run_stencil<double, double, double, double, 1>(ctx, p, w, f, out, partial, nparts, s, gate,
+    return run_stencil<double, double, double, double, 1>(ctx, p, cc, f, out, partial, nparts, s, gate,
                                                           N, bt);
-  return run_stencil<double, double, double, double, 0>(ctx, p, w, nullptr, out, partial, nparts, s,
+  return run_stencil<double, double, double, double, 0>(ctx, p, cc, nullptr, out, partial, nparts, s,
                                                         gate, N, bt);
 }
 
-int launch_stencil_f32(kp_context* ctx, const float* p, const float* w, float* out,
+int launch_stencil_f32(kp_context* ctx, const float* p, const float* cells, int L, int n0, float* out,
                        double* partial, int* nparts, const Scalars* s, int N, const Batch& bt) {
-  return run_stencil<float, float, float, float, 0>(ctx, p, w, nullptr, out, partial, nparts, s,
-                                                    GATE_ACTIVE, N, bt);
+  return run_stencil<float, float, float, float, 0>(ctx, p, Cells<float>{cells, L, n0}, nullptr, out,
+                                                    partial, nparts, s, GATE_ACTIVE, N, bt);
 }
 
-int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* w, const double* f,
-                            float* out, double* partial, int* nparts, const Scalars* s, int N,
-                            const Batch& bt, int gate) {
-  return run_stencil<double, double, float, double, 1>(ctx, x, w, f, out, partial, nparts, s, gate, N,
-                                                       bt);
+int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* cells, int L, int n0,
+                            const double* f, float* out, double* partial, int* nparts,
+                            const Scalars* s, int N, const Batch& bt, int gate) {
+  return run_stencil<double, double, float, double, 1>(ctx, x, Cells<double>{cells, L, n0}, f, out,
+                                                       partial, nparts, s, gate, N, bt);
 }
 
 }  // namespace kp
