@@ -103,22 +103,16 @@ __device__ __forceinline__ void tile_of(int Mt, int order, int& mt, int& nt) {
   }
 }
 
-__device__ __forceinline__ bf16_t f32_to_bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
-}
-
+// float -> output type; 16-bit results round to nearest even (the
+// conversion instructions of gfx950).
 template <typename TO, bool F16>
 __device__ __forceinline__ TO cvt_out(float v) {
   if constexpr (sizeof(TO) == 4) {
     return v;
   } else if constexpr (F16) {
-    _Float16 h = (_Float16)v;
-    return __builtin_bit_cast(bf16_t, h);
+    return __builtin_bit_cast(bf16_t, (_Float16)v);
   } else {
-    return f32_to_bf16_rne(v);
+    return __builtin_bit_cast(bf16_t, (__bf16)v);
   }
 }
 
@@ -215,37 +209,42 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 // accesses only (a __syncthreads would also wait for the register prefetch).
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <int V>
-using IC = std::integral_constant<int, V>;
+// LDS rows hold BK 16-bit values as 16-byte chunks; chunk c of row r sits at
+// slot c ^ (r & 7) (BK = 64, eight chunks) or c ^ ((r >> 2) & 3) (BK = 32, four
+// chunks), so the eight (four) rows read by one fragment load, or written by
+// one store, fall in different banks.  No padding.
+template <int BK>
+__device__ __forceinline__ int swz(int row) {
+  return BK == 64 ? (row & 7) : ((row >> 2) & 3);
+}
 
 // 256 threads = 2 x 2 wavefronts, block tile BM x BN, K tile BK (BK/32
-// 16x16x32 steps).  Operands move as 16-byte vectors of eight 16-bit values.
-// LDS rows hold BK values as 16-byte chunks, chunk c of row r at slot
-// c ^ (r & 7) (BK = 64, eight chunks) or c ^ ((r >> 2) & 3) (BK = 32, four
-// chunks), so that the rows one fragment load touches fall in different
-// banks; no padding.  With SPLIT the A tile is staged twice (hi and lo
-// planes) and every B fragment feeds two MFMAs.  The K tiles are fetched PF
-// tiles ahead into registers (a ring of PF register sets), so a load has PF
-// steps of MFMAs to arrive.
-template <int STAGE, int BM, int BN, int BK, int PF, bool F16, bool SPLIT, typename TO>
+// 16x16x32 steps).  Operands move as 16-byte vectors of eight 16-bit values;
+// the next K tile is fetched into registers while the current one is
+// multiplied.  With SPLIT the A tile is staged twice (hi and lo planes) and
+// every B fragment feeds two MFMAs.  Tiles inside the matrices (all but the
+// ragged edges) take a lean path: global loads from a uniform base plus 32-bit
+// per-thread offsets, no bounds tests, and a division-free epilogue; LDS
+// addresses are per-thread constants in both paths.
+template <int STAGE, int BM, int BN, int BK, bool F16, bool SPLIT, typename TO>
 __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
   if (g.done && g.done[(long long)bo * g.done_stride]) return;
   static_assert(BK == 32 || BK == 64, "K tile");
   constexpr int CH = BK / 8;  // 16-byte chunks per row
-  auto slot = [](int row, int ch) { return (CH == 8 ? (ch ^ (row & 7)) : (ch ^ ((row >> 2) & 3))) * 8; };
   constexpr int NP = SPLIT ? 2 : 1;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int VA = BM * BK / 8 / 256, VB = BN * BK / 8 / 256;  // 16-byte vectors per thread
+  constexpr int RS = 256 / CH;  // rows between a thread's successive vectors
   // Operand tiles; after the K loop the same memory stages the output.
   constexpr int VL = 16 / (int)sizeof(TO);  // output elements per 16-byte vector
   constexpr int LDO = WN + VL;              // padded staging row of one wave
   constexpr int OP_BYTES = (NP * BM + BN) * BK * 2;
   constexpr int STG_BYTES = 4 * 16 * LDO * (int)sizeof(TO);
   __shared__ __attribute__((aligned(16))) unsigned char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
-  auto As = reinterpret_cast<bf16_t(*)[BM][BK]>(smem);
-  auto Bs = reinterpret_cast<bf16_t(*)[BK]>(smem + NP * BM * BK * 2);
+  bf16_t* const sA = reinterpret_cast<bf16_t*>(smem);  // [NP][BM][BK]
+  bf16_t* const sB = sA + NP * BM * BK;                 // [BN][BK]
   const bf16_t* __restrict__ A = (const bf16_t*)g.A + (long long)bi * g.sAb;
   const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
   TO* __restrict__ C = (TO*)g.C + (long long)bo * g.sCb;
@@ -260,32 +259,28 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  u32x4 ra[PF][NP][VA], rb[PF][VB];
-  auto load_vec = [&](const bf16_t* __restrict__ P, long long ld, int rows, int r0, int k0, int e,
-                      u32x4& dst) {
-    const int r = e / CH, c = (e % CH) * 8;
-    const int gr = r0 + r, gk = k0 + c;
-    if (gr < rows && g.vec && gk + 8 <= g.K) {
-      dst = *(const u32x4*)(P + (long long)gr * ld + gk);
-    } else {
-      uint32_t w[4] = {0u, 0u, 0u, 0u};
-      if (gr < rows) {
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t v = (gk + q < g.K) ? (uint32_t)P[(long long)gr * ld + gk + q] : 0u;
-          w[q >> 1] |= v << (16 * (q & 1));
-        }
-      }
-      dst = u32x4{w[0], w[1], w[2], w[3]};
-    }
-  };
-  auto load = [&](int k0, auto sc) {
-    constexpr int S = decltype(sc)::value;
+  // Thread t stores vectors e = t + 256 v: row e / CH = t / CH + RS v, chunk
+  // t % CH; the swizzle of those rows does not depend on v.
+  const int st_row = tid / CH, st_ch = tid % CH;
+  const int st_off = st_row * BK + ((st_ch ^ swz<BK>(st_row)) * 8);
+  // Fragment reads: row base + (lane & 15), chunk ks / 8 + lane / 16.
+  const int rd_sw = swz<BK>(lane & 15);
+  int rdA[BK / 32], rdB[BK / 32];
+#pragma unroll
+  for (int q = 0; q < BK / 32; ++q) {
+    const int ch = (4 * q + (lane >> 4)) ^ rd_sw;
+    rdA[q] = (wm * WM + (lane & 15)) * BK + ch * 8;
+    rdB[q] = (wn * WN + (lane & 15)) * BK + ch * 8;
+  }
+
+  u32x4 ra[NP][VA], rb[VB];
+  auto store_lds = [&]() {
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int t = 0; t < VA; ++t) load_vec(A + p * g.a_lo, g.lda, g.M, m0, k0, tid + 256 * t, ra[S][p][t]);
+      for (int t = 0; t < VA; ++t) *(u32x4*)(sA + (p * BM + RS * t) * BK + st_off) = ra[p][t];
 #pragma unroll
-    for (int t = 0; t < VB; ++t) load_vec(B, g.ldb, g.Nn, n0, k0, tid + 256 * t, rb[S][t]);
+    for (int t = 0; t < VB; ++t) *(u32x4*)(sB + RS * t * BK + st_off) = rb[t];
   };
   auto mfma = [&](const u32x4& a, const u32x4& b, flt4& c) {
     if constexpr (F16)
@@ -295,67 +290,104 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   };
-  // One K tile: registers of ring slot S -> LDS, refill the slot PF tiles
-  // ahead, multiply.
-  auto step = [&](int k0, auto sc) {
-    constexpr int S = decltype(sc)::value;
+  auto multiply = [&]() {
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int t = 0; t < VA; ++t) {
-        const int e = tid + 256 * t, row = e / CH;
-        *(u32x4*)&As[p][row][slot(row, e % CH)] = ra[S][p][t];
-      }
-#pragma unroll
-    for (int t = 0; t < VB; ++t) {
-      const int e = tid + 256 * t, row = e / CH;
-      *(u32x4*)&Bs[row][slot(row, e % CH)] = rb[S][t];
-    }
-    lds_barrier();
-    if (k0 + PF * BK < g.K) load(k0 + PF * BK, sc);
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 32) {
-      const int ch = ks / 8 + (lane >> 4);
+    for (int q = 0; q < BK / 32; ++q) {
       u32x4 bfr[TN];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int row = wn * WN + j * 16 + (lane & 15);
-        bfr[j] = *(const u32x4*)&Bs[row][slot(row, ch)];
-      }
+      for (int j = 0; j < TN; ++j) bfr[j] = *(const u32x4*)(sB + rdB[q] + j * 16 * BK);
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         u32x4 af[TM];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const int row = wm * WM + i * 16 + (lane & 15);
-          af[i] = *(const u32x4*)&As[p][row][slot(row, ch)];
-        }
+        for (int i = 0; i < TM; ++i) af[i] = *(const u32x4*)(sA + rdA[q] + (p * BM + i * 16) * BK);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j) mfma(af[i], bfr[j], acc[i][j]);
       }
     }
-    lds_barrier();
   };
-  load(0, IC<0>());
-  if constexpr (PF == 2) {
-    if (BK < g.K) load(BK, IC<1>());
-    for (int k0 = 0; k0 < g.K; k0 += 2 * BK) {
-      step(k0, IC<0>());
-      if (k0 + BK < g.K) step(k0 + BK, IC<1>());
+
+  const bool interior = m0 + BM <= g.M && n0 + BN <= g.Nn && g.vec && g.K % BK == 0;
+  if (interior) {
+    // Uniform tile origins plus 32-bit per-thread offsets (in elements).
+    const bf16_t* __restrict__ Ab = A + (long long)m0 * g.lda;
+    const bf16_t* __restrict__ Bb = B + (long long)n0 * g.ldb;
+    unsigned offA[VA], offB[VB];
+#pragma unroll
+    for (int t = 0; t < VA; ++t) offA[t] = (unsigned)((st_row + RS * t) * g.lda + st_ch * 8);
+#pragma unroll
+    for (int t = 0; t < VB; ++t) offB[t] = (unsigned)((st_row + RS * t) * g.ldb + st_ch * 8);
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const bf16_t* __restrict__ Ap = Ab + p * g.a_lo + k0;
+#pragma unroll
+        for (int t = 0; t < VA; ++t) ra[p][t] = *(const u32x4*)(Ap + offA[t]);
+      }
+      const bf16_t* __restrict__ Bp = Bb + k0;
+#pragma unroll
+      for (int t = 0; t < VB; ++t) rb[t] = *(const u32x4*)(Bp + offB[t]);
+    };
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+      store_lds();
+      lds_barrier();
+      if (k0 + BK < g.K) load(k0 + BK);
+      multiply();
+      lds_barrier();
     }
   } else {
-    for (int k0 = 0; k0 < g.K; k0 += BK) step(k0, IC<0>());
+    // Ragged tile: element-wise zero fill outside the matrices.
+    auto load_vec = [&](const bf16_t* __restrict__ P, long long ld, int rows, int r, int k0,
+                        u32x4& dst) {
+      const int gk = k0 + st_ch * 8;
+      if (r < rows && g.vec && gk + 8 <= g.K) {
+        dst = *(const u32x4*)(P + (long long)r * ld + gk);
+      } else {
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (r < rows) {
+          for (int q = 0; q < 8; ++q) {
+            const uint32_t v = (gk + q < g.K) ? (uint32_t)P[(long long)r * ld + gk + q] : 0u;
+            w[q >> 1] |= v << (16 * (q & 1));
+          }
+        }
+        dst = u32x4{w[0], w[1], w[2], w[3]};
+      }
+    };
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int t = 0; t < VA; ++t) load_vec(A + p * g.a_lo, g.lda, g.M, m0 + st_row + RS * t, k0, ra[p][t]);
+#pragma unroll
+      for (int t = 0; t < VB; ++t) load_vec(B, g.ldb, g.Nn, n0 + st_row + RS * t, k0, rb[t]);
+    };
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+      store_lds();
+      lds_barrier();
+      if (k0 + BK < g.K) load(k0 + BK);
+      multiply();
+      lds_barrier();
+    }
   }
   __syncthreads();
+
   // Epilogue: every wave passes its 16 x WN accumulator strips through LDS
   // and writes them as 16-byte vectors along n, which is contiguous in memory
-  // whenever sn2 = 1 and the vector stays inside one run of nd columns.
+  // whenever sn2 = 1 and the vector stays inside one run of nd columns.  When
+  // the wave's whole column range lies in one run (always for interior tiles
+  // of the three stages at sizes that are multiples of the tile), the run's
+  // start is computed once per wave instead of per element.
   const float oscale = g.out_div ? (float)(1.0 / g.out_div[(long long)bo * g.div_stride]) : 1.0f;
   TO* stg = reinterpret_cast<TO*>(smem) + wid * 16 * LDO;
   constexpr int VPR = WN / VL;  // vectors per staged row
-  const bool contig = g.om.sn2 == 1;
+  const int nw = n0 + wn * WN;  // first column of the wave
+  const int run_q = nw / g.om.nd, run_r = nw - run_q * g.om.nd;
+  const bool fast = interior && g.om.sn2 == 1 && run_r + WN <= g.om.nd;
+  const long long col0 = (long long)run_q * g.om.sn1 + run_r + (long long)bi * g.om.sb;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     // v_mfma_f32_16x16x32_{bf16,f16} result: item v of lane l is row 4(l/16) + v, column l%16.
@@ -368,11 +400,18 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
 #pragma unroll
     for (int t = 0; t < 16 * VPR / 64; ++t) {
       const int e = lane + 64 * t, r = e / VPR, c = (e % VPR) * VL;
-      const int m = m0 + wm * WM + i * 16 + r, n = n0 + wn * WN + c;
-      if (m >= g.M || n >= g.Nn) continue;
+      const int m = m0 + wm * WM + i * 16 + r, n = nw + c;
       const TO* src = stg + r * LDO + c;
+      if (fast) {
+        TO* dst = C + (long long)m * g.om.sm + col0 + c;
+        if (((uintptr_t)dst & 15u) == 0) {
+          *(u32x4*)dst = *(const u32x4*)src;
+          continue;
+        }
+      }
+      if (m >= g.M || n >= g.Nn) continue;
       TO* dst = C + out_addr(g.om, m, n, bi);
-      if (contig && n + VL <= g.Nn && n % g.om.nd + VL <= g.om.nd && ((uintptr_t)dst & 15u) == 0) {
+      if (g.om.sn2 == 1 && n + VL <= g.Nn && n % g.om.nd + VL <= g.om.nd && ((uintptr_t)dst & 15u) == 0) {
         *(u32x4*)dst = *(const u32x4*)src;
       } else {
         for (int q = 0; q < VL && n + q < g.Nn; ++q) C[out_addr(g.om, m, n + q, bi)] = src[q];
@@ -387,10 +426,10 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // Tile configurations (block rows x block columns [x K tile for 16-bit]).  The
 // autotuner times them per stage; without tuning a size heuristic picks one.
 constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-// 16-bit: {BM, BN, BK, prefetch depth}.
-constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 1},   {128, 64, 64, 1},  {64, 128, 64, 1},
-                                     {128, 128, 64, 1}, {128, 128, 32, 1}, {64, 128, 32, 2},
-                                     {128, 128, 32, 2}, {64, 128, 64, 2}};
+// 16-bit: {BM, BN, BK}.
+constexpr int kCfg16[kTiles16][3] = {{64, 64, 64},   {128, 64, 64},  {64, 128, 64},
+                                     {128, 128, 64}, {128, 128, 32}, {64, 128, 32},
+                                     {256, 128, 32}, {128, 256, 32}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
@@ -425,15 +464,15 @@ int run_gemm_f64(kp_context* ctx, GemmArgs g, int batch, int cfg, int stage) {
   return KP_OK;
 }
 
-template <int STAGE, int BM, int BN, int BK, int PF, typename TO>
+template <int STAGE, int BM, int BN, int BK, typename TO>
 void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
   dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
   if (g.a_lo) {
-    if (f16) hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, true, true, TO>), grid, dim3(256), 0, ctx->stream, g);
-    else hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, false, true, TO>), grid, dim3(256), 0, ctx->stream, g);
+    if (f16) hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, true, true, TO>), grid, dim3(256), 0, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, false, true, TO>), grid, dim3(256), 0, ctx->stream, g);
   } else {
-    if (f16) hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, true, false, TO>), grid, dim3(256), 0, ctx->stream, g);
-    else hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, PF, false, false, TO>), grid, dim3(256), 0, ctx->stream, g);
+    if (f16) hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, true, false, TO>), grid, dim3(256), 0, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, false, false, TO>), grid, dim3(256), 0, ctx->stream, g);
   }
 }
 
@@ -446,14 +485,14 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
   if (cfg < 0 || cfg >= 2 * kTiles16) cfg = heuristic16(g, batch);
   g.order = cfg / kTiles16;
   switch (cfg % kTiles16) {
-    case 0: launch16<STAGE, 64, 64, 64, 1, TO>(ctx, g, batch, f16); break;
-    case 1: launch16<STAGE, 128, 64, 64, 1, TO>(ctx, g, batch, f16); break;
-    case 2: launch16<STAGE, 64, 128, 64, 1, TO>(ctx, g, batch, f16); break;
-    case 3: launch16<STAGE, 128, 128, 64, 1, TO>(ctx, g, batch, f16); break;
-    case 4: launch16<STAGE, 128, 128, 32, 1, TO>(ctx, g, batch, f16); break;
-    case 5: launch16<STAGE, 64, 128, 32, 2, TO>(ctx, g, batch, f16); break;
-    case 6: launch16<STAGE, 128, 128, 32, 2, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 64, 128, 64, 2, TO>(ctx, g, batch, f16); break;
+    case 0: launch16<STAGE, 64, 64, 64, TO>(ctx, g, batch, f16); break;
+    case 1: launch16<STAGE, 128, 64, 64, TO>(ctx, g, batch, f16); break;
+    case 2: launch16<STAGE, 64, 128, 64, TO>(ctx, g, batch, f16); break;
+    case 3: launch16<STAGE, 128, 128, 64, TO>(ctx, g, batch, f16); break;
+    case 4: launch16<STAGE, 128, 128, 32, TO>(ctx, g, batch, f16); break;
+    case 5: launch16<STAGE, 64, 128, 32, TO>(ctx, g, batch, f16); break;
+    case 6: launch16<STAGE, 256, 128, 32, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 128, 256, 32, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
@@ -586,7 +625,6 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         e.bm = sixteen ? kCfg16[t][0] : kCfg64[t][0];
         e.bn = sixteen ? kCfg16[t][1] : kCfg64[t][1];
         e.bk = sixteen ? kCfg16[t][2] : 16;
-        e.depth = sixteen ? kCfg16[t][3] : 1;
         e.order = c / ntile;
         e.ms = avg;
       }

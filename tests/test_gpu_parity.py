@@ -301,7 +301,7 @@ def test_every_tile_configuration_matches(ctx, prec, tol):
     pc = kp.Precond(ctx, 72, precision=prec, factors=F)
     ncfg = 2 * (4 if prec == "fp64" else 8)      # tile shapes x two block orders
     table = pc.autotune(reps=1)
-    assert len(table) == 3 * ncfg and all(t[6] > 0 for t in table)
+    assert len(table) == 3 * ncfg and all(t[5] > 0 for t in table)
     assert {t[4] for t in table} == {0, 1}
     tuned = pc.tiles
     assert all(0 <= t < ncfg for t in tuned)
