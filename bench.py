@@ -283,8 +283,8 @@ def main():
                                 "seed 3; assembly + 3 corrector solves to 1e-8 + a_hom per step"),
                    "precision": prec, "rank": pc.R, "precond": pc.info,
                    "precond_build_s": build_s, "autotune_s": tune_s},
-        "autotune": [{"stage": s, "bm": bm, "bn": bn, "bk": bk, "order": o, "ms": ms}
-                     for s, bm, bn, bk, o, ms in tuning],
+        "autotune": [{"stage": s, "bm": bm, "bn": bn, "bk": bk, "order": o, "circ": d, "ms": ms}
+                     for s, bm, bn, bk, o, d, ms in tuning],
         "iters_per_sec": sum(iters) / elapsed,
         "iters": iters,
         "relres_true": [s["relres_true"] for s in all_stats],

@@ -180,12 +180,12 @@ class Precond:
     def autotune(self, reps: int = 5):
         """Time the tile configurations of the three GEMM stages and keep the fastest.
 
-        Returns [(stage, bm, bn, bk, order, ms), ...] for every configuration timed."""
+        Returns [(stage, bm, bn, bk, order, circ, ms), ...] for every configuration timed."""
         cap = 64
         table = (_lib.TileTiming * cap)()
         n = C.c_int(0)
         check(load().kp_precond_autotune(self.ctx.handle, self.handle, int(reps), table, cap, C.byref(n)))
-        return [(t.stage, t.bm, t.bn, t.bk, t.order, t.ms) for t in table[:min(n.value, cap)]]
+        return [(t.stage, t.bm, t.bn, t.bk, t.order, t.circ, t.ms) for t in table[:min(n.value, cap)]]
 
     @property
     def tiles(self):

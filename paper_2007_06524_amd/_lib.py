@@ -54,7 +54,7 @@ class SolveStats(C.Structure):
 
 class TileTiming(C.Structure):
     _fields_ = [("stage", C.c_int), ("bm", C.c_int), ("bn", C.c_int), ("bk", C.c_int), ("order", C.c_int),
-                ("ms", C.c_double)]
+                ("circ", C.c_int), ("ms", C.c_double)]
 
 
 TIMERS = ("stencil", "gemm_mode3", "gemm_mode2", "gemm_mode1", "vector", "assemble", "residual")

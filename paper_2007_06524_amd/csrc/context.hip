@@ -246,15 +246,36 @@ static int upload_precond(kp_context* ctx, int N, int R, const double* factors, 
     split_rows(c2, RN, n, h2);
     split_rows(b3, RN, n, h3);
     const size_t b16 = 2 * n * RN * sizeof(uint16_t);
+    // Shifted reversed first columns (see kp_precond::circ16), same hi / lo values.
+    const size_t np8 = n + 8, per_k = 2 * 8 * np8;
+    std::vector<uint16_t> hc[3];
+    for (int l = 0; l < 3; ++l) {
+      hc[l].assign((size_t)R * per_k, 0);
+      for (int k = 0; k < R; ++k)
+        for (int sft = 0; sft < 8; ++sft)
+          for (size_t v = 0; v < np8; ++v) {
+            const size_t u = (v + sft) % n;                 // r(u) = c((-u) mod N) = C[0][u]
+            const double x = C(l, k, 0, (int)u);
+            const uint16_t hi = r16(x);
+            hc[l][(size_t)k * per_k + (0 * 8 + sft) * np8 + v] = hi;
+            hc[l][(size_t)k * per_k + (1 * 8 + sft) * np8 + v] = r16(x - back(hi));
+          }
+    }
+    const size_t bc = (size_t)R * per_k * sizeof(uint16_t);
     if ((st = dev_alloc(ctx, (void**)&pc->a1_16, b16)) < 0 ||
         (st = dev_alloc(ctx, (void**)&pc->c2_16, b16)) < 0 ||
-        (st = dev_alloc(ctx, (void**)&pc->b3_16, b16)) < 0) {
+        (st = dev_alloc(ctx, (void**)&pc->b3_16, b16)) < 0 ||
+        (st = dev_alloc(ctx, (void**)&pc->circ16[0], bc)) < 0 ||
+        (st = dev_alloc(ctx, (void**)&pc->circ16[1], bc)) < 0 ||
+        (st = dev_alloc(ctx, (void**)&pc->circ16[2], bc)) < 0) {
       kp_free_precond(pc);
       return st;
     }
     e = hipMemcpyAsync(pc->a1_16, h1.data(), b16, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(pc->c2_16, h2.data(), b16, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(pc->b3_16, h3.data(), b16, hipMemcpyHostToDevice, ctx->stream);
+    for (int l = 0; l < 3 && e == hipSuccess; ++l)
+      e = hipMemcpyAsync(pc->circ16[l], hc[l].data(), bc, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // host staging goes out of scope
   }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -551,6 +572,7 @@ int kp_free_precond(kp_precond* pc) {
   dev_free(ctx, pc->a1_16);
   dev_free(ctx, pc->c2_16);
   dev_free(ctx, pc->b3_16);
+  for (int l = 0; l < 3; ++l) dev_free(ctx, pc->circ16[l]);
   delete pc;
   return KP_OK;
 }

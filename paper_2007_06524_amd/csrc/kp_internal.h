@@ -181,6 +181,12 @@ struct kp_precond {
   kp::bf16_t* a1_16 = nullptr;  // N x 2RN
   kp::bf16_t* c2_16 = nullptr;  // R x N x 2N
   kp::bf16_t* b3_16 = nullptr;  // RN x 2N
+  // The same 16-bit circulants by their first columns, for GEMM kernels that
+  // build the circulant operand in LDS: circ16[l] = [k][plane hi/lo][s][N + 8]
+  // with row s holding r(s), r(s+1), ..., r(s+N+7) of the reversed first column
+  // r(u) = c((-u) mod N) of C_{l+1}^k (indices mod N), so C[j][i..i+7] =
+  // r(u0..u0+7), u0 = (i - j) mod N, is the aligned run at (u0 & ~7) of row u0 & 7.
+  kp::bf16_t* circ16[3] = {nullptr, nullptr, nullptr};
   kp_precond_info info{};
   int tile[3] = {-1, -1, -1};   // tile configuration per GEMM stage (-1: size heuristic)
   int tile_batch[3] = {-1, -1, -1};  // the same, tuned for batched solves
@@ -200,7 +206,7 @@ constexpr int kRedBlocks = 1024;
 constexpr int kMaxPartials = 65536;
 // Number of GEMM tile configurations (double and 16-bit kernels).
 constexpr int kTiles64 = 4;
-constexpr int kTiles16 = 8;
+constexpr int kTiles16 = 10;
 
 // Times every tile configuration for a batch of nsys systems on scratch T, U,
 // X, Z (NULL: the context workspace, nsys = 1) and stores the fastest in tiles[3].

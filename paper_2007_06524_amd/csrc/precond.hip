@@ -63,6 +63,11 @@ struct GemmArgs {
   int bdiv;
   long long sCb;
   int done_stride, div_stride;
+  // Circulant operand by its first columns (kp_precond::circ16 layout), for
+  // k_gemm_16c: A[m][kk] = C_ci[j][i] with j = m mod cn, i = kk mod cn and
+  // ci = m / cn (cmode 0), the batch index bi (cmode 1) or kk / cn (cmode 2).
+  const bf16_t* circ;
+  int cn, cmode;
 };
 
 GemmArgs gemm_args(const void* A, const void* B, void* C, long long M, long long Nn, long long K,
@@ -70,7 +75,7 @@ GemmArgs gemm_args(const void* A, const void* B, void* C, long long M, long long
                    const int* done, long long a_lo, const double* out_div, int bdiv, long long sCb) {
   return GemmArgs{A,  B, C,      (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0,
                   a_lo, out_div, 0, bdiv, sCb, (int)(sizeof(Scalars) / sizeof(int)),
-                  (int)(sizeof(Scalars) / sizeof(double))};
+                  (int)(sizeof(Scalars) / sizeof(double)), nullptr, 0, 0};
 }
 
 __device__ __forceinline__ long long out_addr(const OutMap& o, int m, int n, int b) {
@@ -210,12 +215,68 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // LDS rows hold BK 16-bit values as 16-byte chunks; chunk c of row r sits at
-// slot c ^ (r & 7) (BK = 64, eight chunks) or c ^ ((r >> 2) & 3) (BK = 32, four
-// chunks), so the eight (four) rows read by one fragment load, or written by
-// one store, fall in different banks.  No padding.
+// slot c ^ (r & 7) (BK = 64 or 128: eight or sixteen chunks) or
+// c ^ ((r >> 2) & 3) (BK = 32, four chunks), so the rows read by one fragment
+// load, or written by one store, fall in different banks.  No padding.
 template <int BK>
 __device__ __forceinline__ int swz(int row) {
-  return BK == 64 ? (row & 7) : ((row >> 2) & 3);
+  return BK == 32 ? ((row >> 2) & 3) : (row & 7);
+}
+
+// Epilogue of the 16-bit kernels: every wave passes its 16 x WN accumulator
+// strips through LDS (smem, free again after the K loop) and writes them as
+// 16-byte vectors along n, which is contiguous in memory whenever sn2 = 1 and
+// the vector stays inside one run of nd columns.  When the wave's whole
+// column range lies in one run (always for interior tiles of the three stages
+// at sizes that are multiples of the tile), the run's start is computed once
+// per wave instead of per element.
+template <int BM, int BN, bool F16, typename TO>
+__device__ __forceinline__ void epilogue16(const GemmArgs& g, const flt4 (&acc)[BM / 32][BN / 32],
+                                           unsigned char* smem, TO* __restrict__ C, int m0, int n0,
+                                           int bo, int bi, bool interior) {
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int VL = 16 / (int)sizeof(TO);
+  constexpr int LDO = WN + VL;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const float oscale = g.out_div ? (float)(1.0 / g.out_div[(long long)bo * g.div_stride]) : 1.0f;
+  TO* stg = reinterpret_cast<TO*>(smem) + wid * 16 * LDO;
+  constexpr int VPR = WN / VL;  // vectors per staged row
+  const int nw = n0 + wn * WN;  // first column of the wave
+  const int run_q = nw / g.om.nd, run_r = nw - run_q * g.om.nd;
+  const bool fast = interior && g.om.sn2 == 1 && run_r + WN <= g.om.nd;
+  const long long col0 = (long long)run_q * g.om.sn1 + run_r + (long long)bi * g.om.sb;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    // v_mfma_f32_16x16x32_{bf16,f16} result: item v of lane l is row 4(l/16) + v, column l%16.
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        stg[(4 * (lane >> 4) + v) * LDO + j * 16 + (lane & 15)] = cvt_out<TO, F16>(acc[i][j][v] * oscale);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16 * VPR / 64; ++t) {
+      const int e = lane + 64 * t, r = e / VPR, c = (e % VPR) * VL;
+      const int m = m0 + wm * WM + i * 16 + r, n = nw + c;
+      const TO* src = stg + r * LDO + c;
+      if (fast) {
+        TO* dst = C + (long long)m * g.om.sm + col0 + c;
+        if (((uintptr_t)dst & 15u) == 0) {
+          *(u32x4*)dst = *(const u32x4*)src;
+          continue;
+        }
+      }
+      if (m >= g.M || n >= g.Nn) continue;
+      TO* dst = C + out_addr(g.om, m, n, bi);
+      if (g.om.sn2 == 1 && n + VL <= g.Nn && n % g.om.nd + VL <= g.om.nd && ((uintptr_t)dst & 15u) == 0) {
+        *(u32x4*)dst = *(const u32x4*)src;
+      } else {
+        for (int q = 0; q < VL && n + q < g.Nn; ++q) C[out_addr(g.om, m, n + q, bi)] = src[q];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // 256 threads = 2 x 2 wavefronts, block tile BM x BN, K tile BK (BK/32
@@ -375,50 +436,121 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   }
   __syncthreads();
 
-  // Epilogue: every wave passes its 16 x WN accumulator strips through LDS
-  // and writes them as 16-byte vectors along n, which is contiguous in memory
-  // whenever sn2 = 1 and the vector stays inside one run of nd columns.  When
-  // the wave's whole column range lies in one run (always for interior tiles
-  // of the three stages at sizes that are multiples of the tile), the run's
-  // start is computed once per wave instead of per element.
-  const float oscale = g.out_div ? (float)(1.0 / g.out_div[(long long)bo * g.div_stride]) : 1.0f;
-  TO* stg = reinterpret_cast<TO*>(smem) + wid * 16 * LDO;
-  constexpr int VPR = WN / VL;  // vectors per staged row
-  const int nw = n0 + wn * WN;  // first column of the wave
-  const int run_q = nw / g.om.nd, run_r = nw - run_q * g.om.nd;
-  const bool fast = interior && g.om.sn2 == 1 && run_r + WN <= g.om.nd;
-  const long long col0 = (long long)run_q * g.om.sn1 + run_r + (long long)bi * g.om.sb;
+  epilogue16<BM, BN, F16, TO>(g, acc, smem, C, m0, n0, bo, bi, interior);
+}
+
+// The same product with the circulant operand built in LDS.  Every A tile is
+// a block of one circulant C (the rows of a tile never leave one circulant,
+// nor do the K tiles), and C[j][i..i+7] = r((i - j) mod N ..) is an aligned
+// 16-byte run of one of eight shifted copies of the reversed first column r
+// (kp_precond::circ16), so the block loads those copies (2 planes x 8 x (N+8)
+// values, 8.4 KB at N = 256) once per circulant instead of streaming A tiles;
+// only the data operand B goes through the K loop.  All tiles must be interior
+// (checked by the launcher).  Dynamic LDS: the copies.
+template <int STAGE, int BM, int BN, int BK, bool F16, typename TO>
+__global__ __launch_bounds__(256) void k_gemm_16c(GemmArgs g) {
+  const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
+  if (g.done && g.done[(long long)bo * g.done_stride]) return;
+  static_assert(BK == 32 || BK == 64 || BK == 128, "K tile");
+  constexpr int CH = BK / 8;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int VB = BN * BK / 8 / 256;
+  constexpr int RS = 256 / CH;
+  constexpr int VL = 16 / (int)sizeof(TO);
+  constexpr int LDO = WN + VL;
+  constexpr int OP_BYTES = BN * BK * 2;
+  constexpr int STG_BYTES = 4 * 16 * LDO * (int)sizeof(TO);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
+  extern __shared__ __attribute__((aligned(16))) bf16_t cpy[];  // [2][8][N + 8]
+  bf16_t* const sB = reinterpret_cast<bf16_t*>(smem);
+  const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
+  TO* __restrict__ C = (TO*)g.C + (long long)bo * g.sCb;
+  int mt, nt;
+  tile_of(g.M / BM, g.order, mt, nt);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int N = g.cn, NP8 = N + 8;
+  flt4 acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    // v_mfma_f32_16x16x32_{bf16,f16} result: item v of lane l is row 4(l/16) + v, column l%16.
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+    for (int j = 0; j < TN; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+  // Copies of circulant ci into LDS (16-byte vectors; N + 8 is a multiple of 8).
+  auto fill = [&](int ci) {
+    const u32x4* __restrict__ src = (const u32x4*)(g.circ + (long long)ci * 16 * NP8);
+    u32x4* dst = (u32x4*)cpy;
+    for (int v = tid; v < 2 * NP8; v += 256) dst[v] = src[v];
+  };
+  const int st_row = tid / CH, st_ch = tid % CH;
+  const int st_off = st_row * BK + ((st_ch ^ swz<BK>(st_row)) * 8);
+  const int rd_sw = swz<BK>(lane & 15);
+  int rdB[BK / 32];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        stg[(4 * (lane >> 4) + v) * LDO + j * 16 + (lane & 15)] = cvt_out<TO, F16>(acc[i][j][v] * oscale);
-    __syncthreads();
+  for (int q = 0; q < BK / 32; ++q) rdB[q] = (wn * WN + (lane & 15)) * BK + ((4 * q + (lane >> 4)) ^ rd_sw) * 8;
+  // Row of fragment i inside its circulant: jr + 16 i; K offset of the lane's run: 8 (lane / 16).
+  const int jr = m0 % N + wm * WM + (lane & 15);
+  const int kl = 8 * (lane >> 4);
+
+  const bf16_t* __restrict__ Bb = B + (long long)n0 * g.ldb;
+  unsigned offB[VB];
 #pragma unroll
-    for (int t = 0; t < 16 * VPR / 64; ++t) {
-      const int e = lane + 64 * t, r = e / VPR, c = (e % VPR) * VL;
-      const int m = m0 + wm * WM + i * 16 + r, n = nw + c;
-      const TO* src = stg + r * LDO + c;
-      if (fast) {
-        TO* dst = C + (long long)m * g.om.sm + col0 + c;
-        if (((uintptr_t)dst & 15u) == 0) {
-          *(u32x4*)dst = *(const u32x4*)src;
-          continue;
-        }
-      }
-      if (m >= g.M || n >= g.Nn) continue;
-      TO* dst = C + out_addr(g.om, m, n, bi);
-      if (g.om.sn2 == 1 && n + VL <= g.Nn && n % g.om.nd + VL <= g.om.nd && ((uintptr_t)dst & 15u) == 0) {
-        *(u32x4*)dst = *(const u32x4*)src;
-      } else {
-        for (int q = 0; q < VL && n + q < g.Nn; ++q) C[out_addr(g.om, m, n + q, bi)] = src[q];
-      }
+  for (int t = 0; t < VB; ++t) offB[t] = (unsigned)((st_row + RS * t) * g.ldb + st_ch * 8);
+  u32x4 rb[VB];
+  auto load = [&](int k0) {
+    const bf16_t* __restrict__ Bp = Bb + k0;
+#pragma unroll
+    for (int t = 0; t < VB; ++t) rb[t] = *(const u32x4*)(Bp + offB[t]);
+  };
+  auto mfma = [&](const u32x4& a, const u32x4& b, flt4& c) {
+    if constexpr (F16)
+      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    else
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  };
+
+  int ci = g.cmode == 0 ? m0 / N : (g.cmode == 1 ? bi : 0);
+  fill(ci);
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    if (g.cmode == 2 && k0 / N != ci) {  // the K tiles enter the next circulant
+      ci = k0 / N;
+      fill(ci);
     }
-    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < VB; ++t) *(u32x4*)(sB + RS * t * BK + st_off) = rb[t];
+    lds_barrier();
+    if (k0 + BK < g.K) load(k0 + BK);
+    const int kin = k0 - (k0 / N) * N + kl;  // column of the run inside the circulant
+#pragma unroll
+    for (int q = 0; q < BK / 32; ++q) {
+      u32x4 bfr[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfr[j] = *(const u32x4*)(sB + rdB[q] + j * 16 * BK);
+      u32x4 af[2][TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        int u0 = kin + 32 * q - (jr + 16 * i);
+        if (u0 < 0) u0 += N;
+        const int off = (u0 & 7) * NP8 + (u0 & ~7);
+        af[0][i] = *(const u32x4*)(cpy + off);
+        af[1][i] = *(const u32x4*)(cpy + 8 * NP8 + off);
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) mfma(af[p][i], bfr[j], acc[i][j]);
+    }
+    lds_barrier();
   }
+  __syncthreads();
+  epilogue16<BM, BN, F16, TO>(g, acc, smem, C, m0, n0, bo, bi, true);
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
@@ -426,19 +558,21 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // Tile configurations (block rows x block columns [x K tile for 16-bit]).  The
 // autotuner times them per stage; without tuning a size heuristic picks one.
 constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-// 16-bit: {BM, BN, BK}.
-constexpr int kCfg16[kTiles16][3] = {{64, 64, 64},   {128, 64, 64},  {64, 128, 64},
-                                     {128, 128, 64}, {128, 128, 32}, {64, 128, 32},
-                                     {256, 128, 32}, {128, 256, 32}};
+// 16-bit: {BM, BN, BK, circulant operand built in LDS (k_gemm_16c)}.
+constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 0},  {128, 64, 64, 0},   {64, 128, 64, 0},
+                                     {128, 128, 64, 0}, {128, 128, 32, 0},  {64, 128, 32, 0},
+                                     {64, 128, 64, 1},  {128, 128, 64, 1},  {128, 128, 32, 1},
+                                     {128, 128, 128, 1}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
 }
 
-// Large problems: 64 x 128 x 64 in the XCD-grouped order (the fastest on the
-// N = 256 stages when measured); small ones: 64 x 64.
+// Large problems: 128 x 128 x 64 with the circulant operand in LDS (else the
+// same tile streamed) in the XCD-grouped order, the fastest on the N = 256
+// stages when measured; small ones: 64 x 64.
 int heuristic16(const GemmArgs& g, int batch) {
-  if ((long long)g.M * g.Nn * batch >= 128LL * 128 * 256) return 2 + kTiles16;
+  if ((long long)g.M * g.Nn * batch >= 128LL * 128 * 256) return 7 + kTiles16;
   return 0;
 }
 
@@ -464,10 +598,14 @@ int run_gemm_f64(kp_context* ctx, GemmArgs g, int batch, int cfg, int stage) {
   return KP_OK;
 }
 
-template <int STAGE, int BM, int BN, int BK, typename TO>
+template <int STAGE, int BM, int BN, int BK, bool CIRC, typename TO>
 void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
   dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
-  if (g.a_lo) {
+  if constexpr (CIRC) {
+    const size_t shm = (size_t)16 * (g.cn + 8) * sizeof(bf16_t);
+    if (f16) hipLaunchKernelGGL((k_gemm_16c<STAGE, BM, BN, BK, true, TO>), grid, dim3(256), shm, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16c<STAGE, BM, BN, BK, false, TO>), grid, dim3(256), shm, ctx->stream, g);
+  } else if (g.a_lo) {
     if (f16) hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, true, true, TO>), grid, dim3(256), 0, ctx->stream, g);
     else hipLaunchKernelGGL((k_gemm_16<STAGE, BM, BN, BK, false, true, TO>), grid, dim3(256), 0, ctx->stream, g);
   } else {
@@ -476,23 +614,42 @@ void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
   }
 }
 
+// 16-byte operand loads are legal: K, strides and planes in multiples of 8
+// elements, 16-byte aligned bases.
+int vec_ok(const GemmArgs& g) {
+  return (g.K % 8 == 0) && (g.lda % 8 == 0) && (g.ldb % 8 == 0) && (g.sAb % 8 == 0) && (g.sBb % 8 == 0) &&
+         (g.a_lo % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+}
+
+// Can k_gemm_16c run this product with tile BM x BN x BK?  Every tile
+// interior, the circulant operand available (hi + lo), N a multiple of 8 and
+// of BK, and for row-indexed circulants (cmode 0) the row tiles inside one.
+bool circ_ok(const GemmArgs& g, int BM, int BN, int BK) {
+  return g.circ && g.a_lo && vec_ok(g) && g.cn % 8 == 0 && g.cn % BK == 0 && g.M % BM == 0 &&
+         g.Nn % BN == 0 && g.K % BK == 0 && (g.cmode != 0 || g.cn % BM == 0) &&
+         (g.cmode == 0 || g.M == g.cn);
+}
 // cfg = tile + kTiles16 * order; out of range: size heuristic, order 0.
 // Stages 0 and 1 write 16-bit intermediates, stage 2 the float result.
 template <int STAGE, typename TO>
 int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
-  g.vec = (g.K % 8 == 0) && (g.lda % 8 == 0) && (g.ldb % 8 == 0) && (g.sAb % 8 == 0) &&
-          (g.sBb % 8 == 0) && (g.a_lo % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+  g.vec = vec_ok(g);
   if (cfg < 0 || cfg >= 2 * kTiles16) cfg = heuristic16(g, batch);
   g.order = cfg / kTiles16;
-  switch (cfg % kTiles16) {
-    case 0: launch16<STAGE, 64, 64, 64, TO>(ctx, g, batch, f16); break;
-    case 1: launch16<STAGE, 128, 64, 64, TO>(ctx, g, batch, f16); break;
-    case 2: launch16<STAGE, 64, 128, 64, TO>(ctx, g, batch, f16); break;
-    case 3: launch16<STAGE, 128, 128, 64, TO>(ctx, g, batch, f16); break;
-    case 4: launch16<STAGE, 128, 128, 32, TO>(ctx, g, batch, f16); break;
-    case 5: launch16<STAGE, 64, 128, 32, TO>(ctx, g, batch, f16); break;
-    case 6: launch16<STAGE, 256, 128, 32, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 128, 256, 32, TO>(ctx, g, batch, f16); break;
+  int t = cfg % kTiles16;
+  if (kCfg16[t][3] && !circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]))
+    t = t == 9 ? 3 : (t == 8 ? 4 : (t == 7 ? 3 : 2));  // the same (or nearest) tile through registers
+  switch (t) {
+    case 0: launch16<STAGE, 64, 64, 64, false, TO>(ctx, g, batch, f16); break;
+    case 1: launch16<STAGE, 128, 64, 64, false, TO>(ctx, g, batch, f16); break;
+    case 2: launch16<STAGE, 64, 128, 64, false, TO>(ctx, g, batch, f16); break;
+    case 3: launch16<STAGE, 128, 128, 64, false, TO>(ctx, g, batch, f16); break;
+    case 4: launch16<STAGE, 128, 128, 32, false, TO>(ctx, g, batch, f16); break;
+    case 5: launch16<STAGE, 64, 128, 32, false, TO>(ctx, g, batch, f16); break;
+    case 6: launch16<STAGE, 64, 128, 64, true, TO>(ctx, g, batch, f16); break;
+    case 7: launch16<STAGE, 128, 128, 64, true, TO>(ctx, g, batch, f16); break;
+    case 8: launch16<STAGE, 128, 128, 32, true, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 128, 128, 128, true, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
@@ -508,7 +665,8 @@ struct Stages {
 };
 
 Stages make_stages(int N, int R, const void* x, const void* a1, const void* c2, const void* b3,
-                   void* T, void* U, void* z, int planes, const Scalars* s, bool scaled, int nsys) {
+                   void* T, void* U, void* z, int planes, const Scalars* s, bool scaled, int nsys,
+                   const bf16_t* const* circ = nullptr) {
   const long long n = N, nn = n * n, n3 = nn * n, RN = (long long)R * N;
   const long long p = planes;
   const long long lo_n = planes == 2 ? n : 0, lo_rn = planes == 2 ? RN : 0;
@@ -526,6 +684,15 @@ Stages make_stages(int N, int R, const void* x, const void* a1, const void* c2, 
   // (iii) rows j1, cols (j2,j3), K = (k,i1); natural row-major output.
   st.s3 = gemm_args(a1, U, z, n, nn, RN, p * RN, RN, 0, R * n3, OutMap{nn, 0, 1, 0, INT_MAX}, done,
                     lo_rn, div, 1, n3);
+  if (circ) {  // the same operands by their first columns: C3 (rows), C2 (batch), C1 (K)
+    st.s1.circ = circ[2];
+    st.s1.cmode = 0;
+    st.s2.circ = circ[1];
+    st.s2.cmode = 1;
+    st.s3.circ = circ[0];
+    st.s3.cmode = 2;
+    st.s1.cn = st.s2.cn = st.s3.cn = N;
+  }
   return st;
 }
 
@@ -565,7 +732,7 @@ int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, fl
   if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(bf16_t), &T));
   if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(bf16_t), &U));
   Stages st = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, 2, s, true,
-                          bt.nsys);
+                          bt.nsys, pc->circ16);
   return run_stages(ctx, st, tiles ? tiles : pc->tile, [&](int stage, const GemmArgs& g, int batch, int cfg) {
     if (stage == 0) return run_gemm_16<0, bf16_t>(ctx, g, batch, f16, cfg);
     if (stage == 1) return run_gemm_16<1, bf16_t>(ctx, g, batch, f16, cfg);
@@ -592,7 +759,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
   KP_HIP(hipMemsetAsync(U, 0, nsys * n3 * pc->R * el, ctx->stream));
   KP_HIP(hipMemsetAsync(X, 0, nsys * n3 * el, ctx->stream));
   Stages st = sixteen ? make_stages(pc->N, pc->R, X, pc->a1_16, pc->c2_16, pc->b3_16, T, U, Z, 2,
-                                    nullptr, false, nsys)
+                                    nullptr, false, nsys, pc->circ16)
                       : make_stages(pc->N, pc->R, X, pc->a1_64, pc->c2_64, pc->b3_64, T, U, Z, 1,
                                     nullptr, false, nsys);
   const bool f16 = pc->precision == KP_MIXED_FP16;
@@ -625,6 +792,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         e.bm = sixteen ? kCfg16[t][0] : kCfg64[t][0];
         e.bn = sixteen ? kCfg16[t][1] : kCfg64[t][1];
         e.bk = sixteen ? kCfg16[t][2] : 16;
+        e.circ = sixteen && kCfg16[t][3] && circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]);
         e.order = c / ntile;
         e.ms = avg;
       }

@@ -293,19 +293,22 @@ def test_coeff_update_and_timing(ctx):
     co.free()
 
 
+@pytest.mark.parametrize("N", [72, 128])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed_bf16", 1e-2), ("mixed_fp16", 2e-3)])
-def test_every_tile_configuration_matches(ctx, prec, tol):
+def test_every_tile_configuration_matches(ctx, prec, tol, N):
     """The autotuner's candidates all compute the same operator: tune, then check the
-    apply with the chosen tiles, on a ragged size (N = 72, R = 3)."""
-    F = even_factors(72, 3, seed=72)
-    pc = kp.Precond(ctx, 72, precision=prec, factors=F)
-    ncfg = 2 * (4 if prec == "fp64" else 8)      # tile shapes x two block orders
+    apply with every configuration, on a ragged size (N = 72, R = 3: edge tiles, K not
+    a multiple of the K tile) and on N = 128 (interior tiles: the kernels that build
+    the circulant operand in LDS)."""
+    F = even_factors(N, 3, seed=N)
+    pc = kp.Precond(ctx, N, precision=prec, factors=F)
+    ncfg = 2 * (4 if prec == "fp64" else 10)     # tile shapes x two block orders
     table = pc.autotune(reps=1)
-    assert len(table) == 3 * ncfg and all(t[5] > 0 for t in table)
+    assert len(table) == 3 * ncfg and all(t[6] > 0 for t in table)
     assert {t[4] for t in table} == {0, 1}
     tuned = pc.tiles
     assert all(0 <= t < ncfg for t in tuned)
-    x = random_field(72, seed=8)
+    x = random_field(N, seed=8)
     ref = lr.kron_apply(F, x)
     for c in range(ncfg):
         pc.tiles = (c, c, c)
