@@ -39,6 +39,7 @@ struct Group {
   Batch bt;
   // device buffers (context allocator)
   double* x = nullptr;    // nsys N^3
+  float* x32 = nullptr;   // nsys N^3 (mixed): increments since the last true residual
   double* fp = nullptr;   // nsys N^3, projected right-hand sides
   double* c64 = nullptr;  // ninst L^3 cell values
   float* c32 = nullptr;   // ninst L^3 (mixed)
@@ -102,6 +103,7 @@ int precondition_and_update(kp_context* ctx, BatchState& B, Group& g, int fin_mo
 // r = f - K x in double (into the iterate's precision), ||r||^2; gated systems only.
 int true_residual(kp_context* ctx, BatchState& B, Group& g, int gate, int fin_mode) {
   int np = 0;
+  if (B.mixed) KP_TRY(launch_fold(ctx, g.x, g.x32, g.n3, g.s, g.bt, gate));
   if (B.mixed)
     KP_TRY(launch_resid_f64_to_f32(ctx, g.x, g.c64, g.L, g.n0, g.fp, (float*)g.r, g.part, &np, g.s, g.N,
                                    g.bt, gate));
@@ -117,13 +119,13 @@ int iteration(kp_context* ctx, BatchState& B, Group& g) {
     KP_TRY(launch_stencil_f32(ctx, (const float*)g.p, g.c32, g.L, g.n0, (float*)g.q, g.part, &np, g.s, g.N,
                               g.bt));
     KP_TRY(fin(ctx, g, np, 1, FIN_ALPHA));
-    KP_TRY(launch_update_xr<float>(ctx, g.x, (const float*)g.p, (float*)g.r, (const float*)g.q, g.x16,
+    KP_TRY(launch_update_xr<float>(ctx, g.x, g.x32, (const float*)g.p, (float*)g.r, (const float*)g.q, g.x16,
                                    B.fp16, g.s, g.part, &np, g.n3, g.bt));
   } else {
     KP_TRY(launch_stencil_f64(ctx, (const double*)g.p, g.c64, g.L, g.n0, nullptr, (double*)g.q, g.part, &np,
                               g.s, g.N, g.bt));
     KP_TRY(fin(ctx, g, np, 1, FIN_ALPHA));
-    KP_TRY(launch_update_xr<double>(ctx, g.x, (const double*)g.p, (double*)g.r, (const double*)g.q,
+    KP_TRY(launch_update_xr<double>(ctx, g.x, nullptr, (const double*)g.p, (double*)g.r, (const double*)g.q,
                                     nullptr, 0, g.s, g.part, &np, g.n3, g.bt));
   }
   KP_TRY(fin(ctx, g, np, 1, FIN_RR_CTL));
@@ -161,6 +163,7 @@ int enqueue_chunk(kp_context* ctx, BatchState& B, int iters, bool concurrent) {
 // Projects every system's x to zero mean (x <- x - mean x).
 int project_x(kp_context* ctx, Group& g) {
   int np = 0;
+  if (g.x32) KP_TRY(launch_fold(ctx, g.x, g.x32, g.n3, nullptr, g.bt));
   KP_TRY(launch_sum2(ctx, g.x, g.n3, g.part, &np, g.bt));
   KP_TRY(fin(ctx, g, np, 2, FIN_SUM));
   return launch_project_s(ctx, g.x, g.x, g.n3, g.s, g.bt);
@@ -253,6 +256,8 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
     if (mixed) {
       KP_TRY(B.alloc(&v, ni * nc * sizeof(float))); g.c32 = (float*)v;
       KP_TRY(B.alloc(&v, ns * g.n3 * sizeof(bf16_t))); g.x16 = (bf16_t*)v;
+      KP_TRY(B.alloc(&v, ns * g.n3 * sizeof(float))); g.x32 = (float*)v;
+      KP_HIP(hipMemsetAsync(g.x32, 0, ns * g.n3 * sizeof(float), ctx->stream));
     }
     KP_TRY(B.alloc(&g.r, ns * g.n3 * word));
     KP_TRY(B.alloc(&g.z, ns * g.n3 * word));

@@ -229,43 +229,58 @@ __device__ __forceinline__ void st4(T* __restrict__ p, size_t i, const T (&v)[4]
 }
 
 // Vector kernels: blockIdx.y is the system of the batch (Batch layout).
-template <typename T>
-__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, const T* __restrict__ p,
-                                                   T* __restrict__ r, const T* __restrict__ q,
-                                                   bf16_t* __restrict__ r16, int fp16,
-                                                   const Scalars* __restrict__ s,
-                                                   double* __restrict__ partial, size_t n,
-                                                   size_t vs) {
+// x += alpha p goes to the double x or, with X32, to a float accumulator that
+// k_fold adds into the double x before every true residual (reliable
+// updates: the float part only ever holds the increments since the last one).
+template <typename T, bool X32>
+__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, float* __restrict__ x32,
+                                                   const T* __restrict__ p, T* __restrict__ r,
+                                                   const T* __restrict__ q, bf16_t* __restrict__ r16,
+                                                   int fp16, const Scalars* __restrict__ s,
+                                                   double* __restrict__ partial, size_t n, size_t vs) {
   const int b = blockIdx.y;
   s += b;
   if (s->done) return;
   const size_t off = b * vs;
-  x += off;
+  if (X32)
+    x32 += off;
+  else
+    x += off;
   p += off;
   r += off;
   q += off;
   if (r16) r16 += off;
   const double alpha = s->alpha;
   const T ta = (T)alpha;
+  const float fa = (float)alpha;
   const float sc = (float)s->x16_scale;
   double acc[1] = {0.0};
   const size_t stride = (size_t)gridDim.x * 256, n4 = n / 4;
   for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n4; c += stride) {
     const size_t i = 4 * c;
     T pv[4], rv[4], qv[4];
-    double xv[4];
     ld4(p, i, pv);
     ld4(r, i, rv);
     ld4(q, i, qv);
-    ld4(x, i, xv);
+    if constexpr (X32) {
+      float xv[4];
+      ld4(x32, i, xv);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xv[e] += fa * (float)pv[e];
+      st4(x32, i, xv);
+    } else {
+      double xv[4];
+      ld4(x, i, xv);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xv[e] += alpha * (double)pv[e];
+      st4(x, i, xv);
+    }
     ushort4 h;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      xv[e] += alpha * (double)pv[e];
       rv[e] = rv[e] - ta * qv[e];
       acc[0] += (double)rv[e] * (double)rv[e];
     }
-    st4(x, i, xv);
     st4(r, i, rv);
     if (r16) {
       h.x = to16((float)rv[0] * sc, fp16);
@@ -277,7 +292,10 @@ __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, const
   }
   for (size_t i = 4 * n4 + (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const T pi = p[i];
-    x[i] += alpha * (double)pi;
+    if constexpr (X32)
+      x32[i] += fa * (float)pi;
+    else
+      x[i] += alpha * (double)pi;
     const T rn = r[i] - ta * q[i];
     r[i] = rn;
     if (r16) r16[i] = to16((float)rn * sc, fp16);
@@ -421,6 +439,34 @@ __global__ __launch_bounds__(256) void k_fill(double* __restrict__ a, double v, 
     a[i] = v;
 }
 
+// x += x32, x32 = 0 (gated systems).
+__global__ __launch_bounds__(256) void k_fold(double* __restrict__ x, float* __restrict__ x32, size_t n,
+                                              const Scalars* __restrict__ s, int gate, size_t vs) {
+  const int b = blockIdx.y;
+  if (s && !gate_open(s[b], gate)) return;
+  x += b * vs;
+  x32 += b * vs;
+  const size_t stride = (size_t)gridDim.x * 256, n4 = n / 4;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < n4; c += stride) {
+    const size_t i = 4 * c;
+    double xv[4];
+    float av[4];
+    ld4(x, i, xv);
+    ld4(x32, i, av);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xv[e] += (double)av[e];
+      av[e] = 0.0f;
+    }
+    st4(x, i, xv);
+    st4(x32, i, av);
+  }
+  for (size_t i = 4 * n4 + (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    x[i] += (double)x32[i];
+    x32[i] = 0.0f;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_count_active(const Scalars* __restrict__ s, int nsys,
                                                       int* __restrict__ out) {
   int c = 0;
@@ -489,15 +535,28 @@ int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nval
 }
 
 template <typename T>
-int launch_update_xr(kp_context* ctx, double* x, const T* p, T* r, const T* q, bf16_t* r16,
-                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n,
-                     const Batch& bt) {
+int launch_update_xr(kp_context* ctx, double* x, float* x32, const T* p, T* r, const T* q,
+                     bf16_t* r16, int fp16, const Scalars* s, double* partial, int* nparts,
+                     size_t n, const Batch& bt) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
   const int g = red_blocks(n);
-  hipLaunchKernelGGL(k_update_xr<T>, dim3(g, bt.nsys), dim3(256), 0, ctx->stream, x, p, r, q, r16,
-                     fp16, s, partial, n, bt.vs);
+  if (x32)
+    hipLaunchKernelGGL((k_update_xr<T, true>), dim3(g, bt.nsys), dim3(256), 0, ctx->stream, x, x32, p, r, q,
+                       r16, fp16, s, partial, n, bt.vs);
+  else
+    hipLaunchKernelGGL((k_update_xr<T, false>), dim3(g, bt.nsys), dim3(256), 0, ctx->stream, x, x32, p, r,
+                       q, r16, fp16, s, partial, n, bt.vs);
   KP_HIP(hipGetLastError());
   *nparts = g;
+  return KP_OK;
+}
+
+int launch_fold(kp_context* ctx, double* x, float* x32, size_t n, const Scalars* s, const Batch& bt,
+                int gate) {
+  ScopedTimer tm(ctx, KP_TIMER_VECTOR);
+  hipLaunchKernelGGL(k_fold, dim3(red_blocks(n), bt.nsys), dim3(256), 0, ctx->stream, x, x32, n, s, gate,
+                     bt.vs);
+  KP_HIP(hipGetLastError());
   return KP_OK;
 }
 
@@ -523,10 +582,10 @@ int launch_update_p(kp_context* ctx, const T* z, T* p, const Scalars* s, size_t 
   return KP_OK;
 }
 
-template int launch_update_xr<double>(kp_context*, double*, const double*, double*, const double*,
-                                      bf16_t*, int, const Scalars*, double*, int*, size_t,
-                                      const Batch&);
-template int launch_update_xr<float>(kp_context*, double*, const float*, float*, const float*,
+template int launch_update_xr<double>(kp_context*, double*, float*, const double*, double*,
+                                      const double*, bf16_t*, int, const Scalars*, double*, int*,
+                                      size_t, const Batch&);
+template int launch_update_xr<float>(kp_context*, double*, float*, const float*, float*, const float*,
                                      bf16_t*, int, const Scalars*, double*, int*, size_t,
                                      const Batch&);
 template int launch_prec_dots<double>(kp_context*, const double*, const double*, const double*,

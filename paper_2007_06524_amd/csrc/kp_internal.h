@@ -85,6 +85,7 @@ enum Slot {
   WS_TMP64,                     // double scratch field (apply entry points)
   WS_TMP64B,
   WS_FLAG,                      // one int (cell validation)
+  WS_X32,                       // float accumulator of x increments (mixed)
   WS_COUNT
 };
 
@@ -264,10 +265,15 @@ int launch_cast32_to16(kp_context* ctx, const float* a, bf16_t* b, size_t n, int
                        const Scalars* s, const Batch& bt = Batch(), int gate = GATE_ACTIVE);
 int launch_fill_f64(kp_context* ctx, double* a, double v, size_t n);
 
+// x += alpha p into the double x, or into the float x32 when given (then
+// launch_fold adds x32 into x); r -= alpha q; r16 = 16-bit(r * scale) when given.
 template <typename T>
-int launch_update_xr(kp_context* ctx, double* x, const T* p, T* r, const T* q, bf16_t* r16,
-                     int fp16, const Scalars* s, double* partial, int* nparts, size_t n,
-                     const Batch& bt = Batch());
+int launch_update_xr(kp_context* ctx, double* x, float* x32, const T* p, T* r, const T* q,
+                     bf16_t* r16, int fp16, const Scalars* s, double* partial, int* nparts,
+                     size_t n, const Batch& bt = Batch());
+// x += x32, x32 = 0 for the gated systems (s NULL: all).
+int launch_fold(kp_context* ctx, double* x, float* x32, size_t n, const Scalars* s,
+                const Batch& bt = Batch(), int gate = GATE_ACTIVE);
 template <typename T>
 int launch_prec_dots(kp_context* ctx, const T* z, const T* r, const T* q, const Scalars* s,
                      double* partial, int* nparts, size_t n, const Batch& bt = Batch());

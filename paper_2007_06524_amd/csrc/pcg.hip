@@ -8,7 +8,9 @@
 // Mixed: float vectors, float stencil on float cell values, BF16/FP16 MFMA
 // preconditioner, flexible PCG (Polak-Ribiere beta, which tolerates a
 // preconditioner that is only approximately linear and symmetric because of
-// rounding); x, dot products, norms and the zero-mean projection in double;
+// rounding); dot products, norms and the zero-mean projection in double; x in
+// double, its increments accumulated in float and added into it before every
+// true residual;
 // every `replace_every` iterations the recursive residual is replaced by the
 // true residual f - K x computed in double from the double cell values.
 //
@@ -39,6 +41,7 @@ struct Solver {
   double* part;
   double* fp;        // projected right-hand side (double)
   double* x;
+  float* x32;        // mixed: increments of x since the last true residual
   void *r, *z, *p, *q;
   bf16_t* x16;
   int np = 0;
@@ -51,6 +54,7 @@ int fin(Solver& S, int nvals, int mode) {
 // r = f - K x (double), ||r||^2 -> s->rr (no iteration counted); convergence flag.
 int true_residual(Solver& S, bool into_r) {
   if (S.mixed) {
+    KP_TRY(launch_fold(S.ctx, S.x, S.x32, S.n3, nullptr));
     // double residual into the double scratch, then (optionally) into the float r.
     void* r64;
     KP_TRY(ws_get(S.ctx, WS_TMP64B, S.n3 * sizeof(double), &r64));
@@ -92,12 +96,13 @@ int iteration(Solver& S, bool replace) {
   if (S.mixed) {
     KP_TRY(launch_stencil_f32(S.ctx, (const float*)S.p, S.c->cells32, S.c->L, S.c->n0, (float*)S.q, S.part, &S.np, S.s, S.N));
     KP_TRY(fin(S, 1, FIN_ALPHA));
-    KP_TRY(launch_update_xr<float>(S.ctx, S.x, (const float*)S.p, (float*)S.r, (const float*)S.q,
+    KP_TRY(launch_update_xr<float>(S.ctx, S.x, S.x32, (const float*)S.p, (float*)S.r, (const float*)S.q,
                                    S.x16, S.fp16, S.s, S.part, &S.np, S.n3));
     KP_TRY(fin(S, 1, FIN_RR));
     if (replace) {
       void* r64;
       KP_TRY(ws_get(S.ctx, WS_TMP64B, S.n3 * sizeof(double), &r64));
+      KP_TRY(launch_fold(S.ctx, S.x, S.x32, S.n3, S.s));
       KP_TRY(launch_resid_f64_to_f32(S.ctx, S.x, S.c->cells, S.c->L, S.c->n0, S.fp, (float*)S.r, S.part, &S.np, S.s, S.N));
       KP_TRY(fin(S, 1, FIN_RR_NOCOUNT));
       KP_TRY(launch_cast32_to16(S.ctx, (const float*)S.r, S.x16, S.n3, S.fp16, S.s));
@@ -106,7 +111,7 @@ int iteration(Solver& S, bool replace) {
   }
   KP_TRY(launch_stencil_f64(S.ctx, (const double*)S.p, S.c->cells, S.c->L, S.c->n0, nullptr, (double*)S.q, S.part, &S.np, S.s, S.N));
   KP_TRY(fin(S, 1, FIN_ALPHA));
-  KP_TRY(launch_update_xr<double>(S.ctx, S.x, (const double*)S.p, (double*)S.r, (const double*)S.q,
+  KP_TRY(launch_update_xr<double>(S.ctx, S.x, nullptr, (const double*)S.p, (double*)S.r, (const double*)S.q,
                                   nullptr, 0, S.s, S.part, &S.np, S.n3));
   KP_TRY(fin(S, 1, FIN_RR));
   return precondition_and_update(S, FIN_PREC, true);
@@ -170,10 +175,14 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   KP_TRY(ws_get(ctx, WS_P, vb, &S.p));
   KP_TRY(ws_get(ctx, WS_Q, vb, &S.q));
   S.x16 = nullptr;
+  S.x32 = nullptr;
   if (mixed) {
     void* xv;
     KP_TRY(ws_get(ctx, WS_X16, S.n3 * sizeof(bf16_t), &xv));
     S.x16 = (bf16_t*)xv;
+    KP_TRY(ws_get(ctx, WS_X32, S.n3 * sizeof(float), &xv));
+    S.x32 = (float*)xv;
+    KP_HIP(hipMemsetAsync(S.x32, 0, S.n3 * sizeof(float), ctx->stream));
   }
   S.s = (Scalars*)sv;
   S.part = (double*)pv;
@@ -291,6 +300,7 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   st.relres_true = std::sqrt(rr_true / ff);
 
   // x <- x - mean(x)
+  if (mixed) KP_TRY(launch_fold(ctx, S.x, S.x32, S.n3, nullptr));
   KP_TRY(launch_sum2(ctx, x_dev, S.n3, S.part, &S.np));
   KP_TRY(fin(S, 2, FIN_SUM));
   KP_TRY(read_scalars(S, &h));
