@@ -47,6 +47,7 @@ struct Group {
   bf16_t* x16 = nullptr;
   void *T = nullptr, *U = nullptr;
   double* part = nullptr;
+  size_t part_cap = 0;  // doubles of part per system
   Scalars* s = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t joined = nullptr;
@@ -86,9 +87,12 @@ int fin(kp_context* ctx, Group& g, int np, int nvals, int mode) {
 int precondition_and_update(kp_context* ctx, BatchState& B, Group& g, int fin_mode, bool have_q) {
   int np = 0;
   if (B.mixed) {
-    KP_TRY(launch_precond_16(ctx, g.pc, g.x16, (float*)g.z, g.s, g.bt, g.T, g.U, g.pc->tile_batch));
-    KP_TRY(launch_prec_dots<float>(ctx, (const float*)g.z, (const float*)g.r,
-                                   have_q ? (const float*)g.q : nullptr, g.s, g.part, &np, g.n3, g.bt));
+    const PrecDots dots{(const float*)g.r, have_q ? (const float*)g.q : nullptr, g.part, g.part_cap};
+    KP_TRY(launch_precond_16(ctx, g.pc, g.x16, (float*)g.z, g.s, g.bt, g.T, g.U, g.pc->tile_batch, &dots,
+                             &np));
+    if (np == 0)
+      KP_TRY(launch_prec_dots<float>(ctx, (const float*)g.z, (const float*)g.r,
+                                     have_q ? (const float*)g.q : nullptr, g.s, g.part, &np, g.n3, g.bt));
     KP_TRY(fin(ctx, g, np, 5, fin_mode));
     return launch_update_p<float>(ctx, (const float*)g.z, (float*)g.p, g.s, g.n3, g.bt);
   }
@@ -267,6 +271,7 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
     KP_TRY(B.alloc(&g.T, ns * R * g.n3 * el));
     KP_TRY(B.alloc(&g.U, ns * R * g.n3 * el));
     KP_TRY(B.alloc(&v, ns * parts * sizeof(double))); g.part = (double*)v;
+    g.part_cap = parts;
     KP_TRY(B.alloc(&v, ns * sizeof(Scalars))); g.s = (Scalars*)v;
   }
   {

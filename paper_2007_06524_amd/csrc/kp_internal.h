@@ -244,10 +244,21 @@ int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, d
                        const Scalars* s, const Batch& bt = Batch(), void* T = nullptr,
                        void* U = nullptr, const int* tiles = nullptr);
 // x16 holds c * r rounded to 16 bits, with c = s[b].x16_scale when s is given
-// (a power of two; 1 without s); the result z is divided by c again.
+// (a power of two; 1 without s); the result z is divided by c again.  With
+// dots, the last stage also leaves block partials of <r,z>, <q,z>, sum z,
+// sum r, sum q (the k_prec_dots values) in dots->part, laid out as a 5-value
+// reduction with *dot_parts blocks per system; *dot_parts = 0 when they did
+// not fit in dots->cap doubles per system (then nothing was written).
+struct PrecDots {
+  const float* r;
+  const float* q;  // may be NULL
+  double* part;
+  size_t cap;      // doubles available per system
+};
 int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, float* z,
                       const Scalars* s, const Batch& bt = Batch(), void* T = nullptr,
-                      void* U = nullptr, const int* tiles = nullptr);
+                      void* U = nullptr, const int* tiles = nullptr, const PrecDots* dots = nullptr,
+                      int* dot_parts = nullptr);
 
 // Vector kernels (double vectors: T = double; mixed: T = float).  All take a
 // batch: vectors at + b * bt.vs, scalars s + b.

@@ -79,9 +79,14 @@ int true_residual(Solver& S, bool into_r) {
 // z = M r; rho, mean(z), beta from the dot products; p = (z - mz) + beta p.
 int precondition_and_update(Solver& S, int fin_mode, bool have_q) {
   if (S.mixed) {
-    KP_TRY(launch_precond_16(S.ctx, S.pc, S.x16, (float*)S.z, S.s));
-    KP_TRY(launch_prec_dots<float>(S.ctx, (const float*)S.z, (const float*)S.r,
-                                   have_q ? (const float*)S.q : nullptr, S.s, S.part, &S.np, S.n3));
+    // The last GEMM stage computes the dot products of z as it writes z.
+    const PrecDots dots{(const float*)S.r, have_q ? (const float*)S.q : nullptr, S.part,
+                        (size_t)kMaxPartials * 8};
+    KP_TRY(launch_precond_16(S.ctx, S.pc, S.x16, (float*)S.z, S.s, Batch(), nullptr, nullptr, nullptr,
+                             &dots, &S.np));
+    if (S.np == 0)
+      KP_TRY(launch_prec_dots<float>(S.ctx, (const float*)S.z, (const float*)S.r,
+                                     have_q ? (const float*)S.q : nullptr, S.s, S.part, &S.np, S.n3));
     KP_TRY(fin(S, 5, fin_mode));
     return launch_update_p<float>(S.ctx, (const float*)S.z, (float*)S.p, S.s, S.n3);
   }

@@ -68,6 +68,12 @@ struct GemmArgs {
   // ci = m / cn (cmode 0), the batch index bi (cmode 1) or kk / cn (cmode 2).
   const bf16_t* circ;
   int cn, cmode;
+  // Optional dot products of the result z with r and q at the same positions
+  // (float vectors, stride sCb per system): block partials of <r,z>, <q,z>,
+  // sum z, sum r, sum q at dpart[bo * 5 G + v G + block], G = blocks per system.
+  const float* dr;
+  const float* dq;
+  double* dpart;
 };
 
 GemmArgs gemm_args(const void* A, const void* B, void* C, long long M, long long Nn, long long K,
@@ -75,7 +81,7 @@ GemmArgs gemm_args(const void* A, const void* B, void* C, long long M, long long
                    const int* done, long long a_lo, const double* out_div, int bdiv, long long sCb) {
   return GemmArgs{A,  B, C,      (int)M, (int)Nn, (int)K, lda, ldb, sAb, sBb, om, done, 0,
                   a_lo, out_div, 0, bdiv, sCb, (int)(sizeof(Scalars) / sizeof(int)),
-                  (int)(sizeof(Scalars) / sizeof(double)), nullptr, 0, 0};
+                  (int)(sizeof(Scalars) / sizeof(double)), nullptr, 0, 0, nullptr, nullptr, nullptr};
 }
 
 __device__ __forceinline__ long long out_addr(const OutMap& o, int m, int n, int b) {
@@ -223,29 +229,43 @@ __device__ __forceinline__ int swz(int row) {
   return BK == 32 ? ((row >> 2) & 3) : (row & 7);
 }
 
-// Epilogue of the 16-bit kernels: every wave passes its 16 x WN accumulator
-// strips through LDS (smem, free again after the K loop) and writes them as
-// 16-byte vectors along n, which is contiguous in memory whenever sn2 = 1 and
-// the vector stays inside one run of nd columns.  When the wave's whole
-// column range lies in one run (always for interior tiles of the three stages
-// at sizes that are multiples of the tile), the run's start is computed once
-// per wave instead of per element.
+// Epilogue of the 16-bit kernels.  Step i stages rows i*16 .. i*16+15 of both
+// wave rows (32 block rows x BN columns) in LDS (smem, free again after the K
+// loop) and writes them as 16-byte vectors along n, each block row as one
+// contiguous run of BN values where the output map allows (sn2 = 1 and the
+// block's column range inside one run of nd columns; always for interior
+// tiles of the three stages at sizes that are multiples of the tile), which
+// writes whole cache lines (partially written lines cost a fetch).  The run's
+// start is computed once per block instead of per element.
 template <int BM, int BN, bool F16, typename TO>
 __device__ __forceinline__ void epilogue16(const GemmArgs& g, const flt4 (&acc)[BM / 32][BN / 32],
                                            unsigned char* smem, TO* __restrict__ C, int m0, int n0,
                                            int bo, int bi, bool interior) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
-  constexpr int VL = 16 / (int)sizeof(TO);
-  constexpr int LDO = WN + VL;
+  constexpr int VL = 16 / (int)sizeof(TO);  // output elements per 16-byte vector
+  constexpr int LDB = BN + VL;              // padded staging row
+  constexpr int VPR = BN / VL;              // vectors per block row
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   const float oscale = g.out_div ? (float)(1.0 / g.out_div[(long long)bo * g.div_stride]) : 1.0f;
-  TO* stg = reinterpret_cast<TO*>(smem) + wid * 16 * LDO;
-  constexpr int VPR = WN / VL;  // vectors per staged row
-  const int nw = n0 + wn * WN;  // first column of the wave
-  const int run_q = nw / g.om.nd, run_r = nw - run_q * g.om.nd;
-  const bool fast = interior && g.om.sn2 == 1 && run_r + WN <= g.om.nd;
+  TO* stg = reinterpret_cast<TO*>(smem);
+  const int run_q = n0 / g.om.nd, run_r = n0 - run_q * g.om.nd;
+  const bool fast = interior && g.om.sn2 == 1 && run_r + BN <= g.om.nd;
   const long long col0 = (long long)run_q * g.om.sn1 + run_r + (long long)bi * g.om.sb;
+  // Fused dot products (float results only; r, q at the same index as z).
+  constexpr bool DOTS = sizeof(TO) == 4;
+  double dacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool dots = DOTS && g.dpart;
+  const float* dr = dots ? g.dr + (long long)bo * g.sCb : nullptr;
+  const float* dq = dots && g.dq ? g.dq + (long long)bo * g.sCb : nullptr;
+  auto dot1 = [&](long long idx, float zv) {
+    const double z = zv, r = dr[idx], q = dq ? (double)dq[idx] : 0.0;
+    dacc[0] += r * z;
+    dacc[1] += q * z;
+    dacc[2] += z;
+    dacc[3] += r;
+    dacc[4] += q;
+  };
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     // v_mfma_f32_16x16x32_{bf16,f16} result: item v of lane l is row 4(l/16) + v, column l%16.
@@ -253,29 +273,67 @@ __device__ __forceinline__ void epilogue16(const GemmArgs& g, const flt4 (&acc)[
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        stg[(4 * (lane >> 4) + v) * LDO + j * 16 + (lane & 15)] = cvt_out<TO, F16>(acc[i][j][v] * oscale);
+        stg[(wm * 16 + 4 * (lane >> 4) + v) * LDB + wn * WN + j * 16 + (lane & 15)] =
+            cvt_out<TO, F16>(acc[i][j][v] * oscale);
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 16 * VPR / 64; ++t) {
-      const int e = lane + 64 * t, r = e / VPR, c = (e % VPR) * VL;
-      const int m = m0 + wm * WM + i * 16 + r, n = nw + c;
-      const TO* src = stg + r * LDO + c;
+    for (int t = 0; t < 32 * VPR / 256; ++t) {
+      const int e = tid + 256 * t, r = e / VPR, c = (e % VPR) * VL;
+      const int m = m0 + (r >> 4) * WM + i * 16 + (r & 15), n = n0 + c;
+      const TO* src = stg + r * LDB + c;
       if (fast) {
-        TO* dst = C + (long long)m * g.om.sm + col0 + c;
+        const long long idx = (long long)m * g.om.sm + col0 + c;
+        TO* dst = C + idx;
         if (((uintptr_t)dst & 15u) == 0) {
-          *(u32x4*)dst = *(const u32x4*)src;
+          const u32x4 v = *(const u32x4*)src;
+          *(u32x4*)dst = v;
+          if constexpr (DOTS) {
+            if (dots) {
+              const flt4 zv = __builtin_bit_cast(flt4, v);
+              const flt4 rv = *(const flt4*)(dr + idx);
+              const flt4 qv = dq ? *(const flt4*)(dq + idx) : flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const double z = zv[e], r = rv[e], q = qv[e];
+                dacc[0] += r * z;
+                dacc[1] += q * z;
+                dacc[2] += z;
+                dacc[3] += r;
+                dacc[4] += q;
+              }
+            }
+          }
           continue;
         }
       }
       if (m >= g.M || n >= g.Nn) continue;
-      TO* dst = C + out_addr(g.om, m, n, bi);
-      if (g.om.sn2 == 1 && n + VL <= g.Nn && n % g.om.nd + VL <= g.om.nd && ((uintptr_t)dst & 15u) == 0) {
-        *(u32x4*)dst = *(const u32x4*)src;
-      } else {
-        for (int q = 0; q < VL && n + q < g.Nn; ++q) C[out_addr(g.om, m, n + q, bi)] = src[q];
+      for (int q = 0; q < VL && n + q < g.Nn; ++q) {
+        const long long idx = out_addr(g.om, m, n + q, bi);
+        C[idx] = src[q];
+        if constexpr (DOTS) {
+          if (dots) dot1(idx, (float)src[q]);
+        }
       }
     }
     __syncthreads();
+  }
+  if constexpr (DOTS) {
+    if (dots) {
+      // Block sums in a fixed order: wave shuffles, then the four waves.
+      double* red = reinterpret_cast<double*>(smem);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        double x = dacc[v];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[v * 4 + wid] = x;
+      }
+      __syncthreads();
+      if (tid < 5) {
+        const int G = gridDim.x;
+        g.dpart[((long long)bo * 5 + tid) * G + blockIdx.x] =
+            (red[tid * 4 + 0] + red[tid * 4 + 1]) + (red[tid * 4 + 2] + red[tid * 4 + 3]);
+      }
+    }
   }
 }
 
@@ -300,9 +358,8 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
   constexpr int RS = 256 / CH;  // rows between a thread's successive vectors
   // Operand tiles; after the K loop the same memory stages the output.
   constexpr int VL = 16 / (int)sizeof(TO);  // output elements per 16-byte vector
-  constexpr int LDO = WN + VL;              // padded staging row of one wave
   constexpr int OP_BYTES = (NP * BM + BN) * BK * 2;
-  constexpr int STG_BYTES = 4 * 16 * LDO * (int)sizeof(TO);
+  constexpr int STG_BYTES = 32 * (BN + VL) * (int)sizeof(TO);
   __shared__ __attribute__((aligned(16))) unsigned char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
   bf16_t* const sA = reinterpret_cast<bf16_t*>(smem);  // [NP][BM][BK]
   bf16_t* const sB = sA + NP * BM * BK;                 // [BN][BK]
@@ -458,9 +515,8 @@ __global__ __launch_bounds__(256) void k_gemm_16c(GemmArgs g) {
   constexpr int VB = BN * BK / 8 / 256;
   constexpr int RS = 256 / CH;
   constexpr int VL = 16 / (int)sizeof(TO);
-  constexpr int LDO = WN + VL;
   constexpr int OP_BYTES = BN * BK * 2;
-  constexpr int STG_BYTES = 4 * 16 * LDO * (int)sizeof(TO);
+  constexpr int STG_BYTES = 32 * (BN + VL) * (int)sizeof(TO);
   __shared__ __attribute__((aligned(16))) unsigned char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
   extern __shared__ __attribute__((aligned(16))) bf16_t cpy[];  // [2][8][N + 8]
   bf16_t* const sB = reinterpret_cast<bf16_t*>(smem);
@@ -629,16 +685,31 @@ bool circ_ok(const GemmArgs& g, int BM, int BN, int BK) {
          g.Nn % BN == 0 && g.K % BK == 0 && (g.cmode != 0 || g.cn % BM == 0) &&
          (g.cmode == 0 || g.M == g.cn);
 }
+// The tile configuration a 16-bit launch uses: cfg = tile + kTiles16 * order
+// (out of range: the size heuristic); a circulant-operand tile that cannot run
+// this product becomes the same (or nearest) tile through registers.
+int resolve16(const GemmArgs& g, int batch, int cfg, int* order) {
+  if (cfg < 0 || cfg >= 2 * kTiles16) cfg = heuristic16(g, batch);
+  *order = cfg / kTiles16;
+  int t = cfg % kTiles16;
+  if (kCfg16[t][3] && !circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]))
+    t = t == 9 ? 3 : (t == 8 ? 4 : (t == 7 ? 3 : 2));
+  return t;
+}
+
+// Blocks per system of a 16-bit launch.
+int blocks16(const GemmArgs& g, int batch, int cfg) {
+  int order;
+  const int t = resolve16(g, batch, cfg, &order);
+  return ((g.Nn + kCfg16[t][1] - 1) / kCfg16[t][1]) * ((g.M + kCfg16[t][0] - 1) / kCfg16[t][0]);
+}
+
 // cfg = tile + kTiles16 * order; out of range: size heuristic, order 0.
 // Stages 0 and 1 write 16-bit intermediates, stage 2 the float result.
 template <int STAGE, typename TO>
 int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
   g.vec = vec_ok(g);
-  if (cfg < 0 || cfg >= 2 * kTiles16) cfg = heuristic16(g, batch);
-  g.order = cfg / kTiles16;
-  int t = cfg % kTiles16;
-  if (kCfg16[t][3] && !circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]))
-    t = t == 9 ? 3 : (t == 8 ? 4 : (t == 7 ? 3 : 2));  // the same (or nearest) tile through registers
+  const int t = resolve16(g, batch, cfg, &g.order);
   switch (t) {
     case 0: launch16<STAGE, 64, 64, 64, false, TO>(ctx, g, batch, f16); break;
     case 1: launch16<STAGE, 128, 64, 64, false, TO>(ctx, g, batch, f16); break;
@@ -726,14 +797,27 @@ int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, d
 }
 
 int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, float* z,
-                      const Scalars* s, const Batch& bt, void* T, void* U, const int* tiles) {
+                      const Scalars* s, const Batch& bt, void* T, void* U, const int* tiles,
+                      const PrecDots* dots, int* dot_parts) {
   const size_t n3 = (size_t)pc->N * pc->N * pc->N;
   const bool f16 = pc->precision == KP_MIXED_FP16;
   if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(bf16_t), &T));
   if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(bf16_t), &U));
   Stages st = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, 2, s, true,
                           bt.nsys, pc->circ16);
-  return run_stages(ctx, st, tiles ? tiles : pc->tile, [&](int stage, const GemmArgs& g, int batch, int cfg) {
+  if (!tiles) tiles = pc->tile;
+  if (dot_parts) *dot_parts = 0;
+  if (dots) {
+    st.s3.vec = vec_ok(st.s3);
+    const int G = blocks16(st.s3, bt.nsys, tiles[2]);
+    if ((size_t)5 * G <= dots->cap) {  // else the caller reduces z itself
+      st.s3.dr = dots->r;
+      st.s3.dq = dots->q;
+      st.s3.dpart = dots->part;
+      *dot_parts = G;
+    }
+  }
+  return run_stages(ctx, st, tiles, [&](int stage, const GemmArgs& g, int batch, int cfg) {
     if (stage == 0) return run_gemm_16<0, bf16_t>(ctx, g, batch, f16, cfg);
     if (stage == 1) return run_gemm_16<1, bf16_t>(ctx, g, batch, f16, cfg);
     return run_gemm_16<2, float>(ctx, g, batch, f16, cfg);
