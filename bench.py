@@ -30,6 +30,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "c3_mixed_bf16_n256_kernels.md")
+# Kernel names of the timed classes in that profile (the GEMM stage is the
+# first template argument).
+TRAFFIC_PATTERNS = {
+    "mixed_bf16": {"gemm_mode3": r"k_gemm_16c?<0,", "gemm_mode2": r"k_gemm_16c?<1,",
+                   "gemm_mode1": r"k_gemm_16c?<2,", "stencil": r"k_stencil<float, float, float, float, 0>"},
+    "mixed_fp16": {},
+    "fp64": {},
+}
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp64": 78.6}
 
 
@@ -200,6 +209,7 @@ def main():
     import torch
 
     import paper_2007_06524_amd as kp
+    from paper_2007_06524_amd.profiling import kernel_source_digest, measured_traffic
     from workloads import CONFIGS, config_cells
 
     if args.batched_only:
@@ -270,6 +280,14 @@ def main():
     d = kernels[dominant]
     roofline = {"kernel": dominant, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
                 "unit": d["unit"], "frac": d["frac"], "traffic": None}
+    # HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    # FETCH_SIZE / WRITE_SIZE summary, only while the kernel sources are the ones
+    # it was measured with.
+    tr = measured_traffic(TRAFFIC_PROFILE, TRAFFIC_PATTERNS[prec].get(dominant, "$^"))
+    if tr and tr["digest"] == kernel_source_digest():
+        roofline["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
+        roofline["traffic_detail"] = {"fetch": tr["fetch_bytes"], "write": tr["write_bytes"],
+                                      "kernel": tr["kernel"], "source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
 
     result = {
         "metric": "PCG solves/sec to rel-res 1e-8 at N=256^3",

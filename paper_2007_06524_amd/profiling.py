@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the solver's kernels.
 
     python -m paper_2007_06524_amd.profiling --trace DIR [--fetch DIR] [--write DIR]
-        [--copy-mib M] [--out FILE] [--title TEXT] [--command TEXT ...]
+        [--copy-mib M] [--out FILE] [--title TEXT] [--command TEXT ...] [--digest]
 
 DIR is a rocprofv3 output directory (CSV files from --output-format csv, or
 the rocpd SQLite database).  The summary is a Markdown table per kernel:
@@ -9,7 +9,9 @@ launches, average duration, and, when counter runs are given, the average
 FETCH_SIZE / WRITE_SIZE per launch.  Counter values are scaled by the ratio
 of the known traffic of the calibration copy kernel (an elementwise kernel
 that reads and writes M MiB, launched first by bench.py --copy-probe-mib M)
-to what the same counter reports for it.
+to what the same counter reports for it.  With --digest the summary records
+a digest of the kernel sources, so that a reader (bench.py) can tell whether
+the counters still describe the kernels as built.
 """
 
 from __future__ import annotations
@@ -93,7 +95,50 @@ def _calibration(counts, copy_mib):
     return known / reported if reported > 0 else None
 
 
-def summarize(trace, fetch=None, write=None, copy_mib=0, title="", commands=()):
+def kernel_source_digest(root=None):
+    """sha256 over the GPU kernel sources (csrc/*.hip and csrc/*.h, sorted by name)."""
+    import hashlib
+    root = root or os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(root, "csrc", "*.hip")) + glob.glob(os.path.join(root, "csrc", "*.h"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+DIGEST_LINE = "Kernel source digest (sha256 of csrc/*.hip and csrc/*.h): "
+
+
+def measured_traffic(summary_path, pattern):
+    """Fetch and write bytes per launch of the kernel matching `pattern` (a regular
+    expression; of several rows the one with the most launches) in a summary this
+    module wrote, with the kernel source digest recorded there; None if absent."""
+    import re
+    if not os.path.exists(summary_path):
+        return None
+    digest, best = None, None
+    with open(summary_path) as fh:
+        for line in fh:
+            if line.startswith(DIGEST_LINE):
+                digest = line[len(DIGEST_LINE):].strip()
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) != 7 or not re.search(pattern, cells[0]):
+                continue
+            try:
+                launches, fetch, write = int(cells[1]), float(cells[5]), float(cells[6])
+            except ValueError:
+                continue
+            if best is None or launches > best["launches"]:
+                best = {"kernel": cells[0].strip("`"), "launches": launches,
+                        "fetch_bytes": fetch * 1e6, "write_bytes": write * 1e6}
+    if best is None:
+        return None
+    best["digest"] = digest
+    return best
+
+
+def summarize(trace, fetch=None, write=None, copy_mib=0, title="", commands=(), digest=None):
     dur = kernel_durations(trace)
     fc = kernel_counters(fetch, "FETCH_SIZE") if fetch else {}
     wc = kernel_counters(write, "WRITE_SIZE") if write else {}
@@ -107,6 +152,8 @@ def summarize(trace, fetch=None, write=None, copy_mib=0, title="", commands=()):
         lines += ["Commands (run from the repository root on the GPU box):", "", "```"]
         lines += list(commands)
         lines += ["```", ""]
+    if digest:
+        lines += [DIGEST_LINE + digest, ""]
     if fetch or write:
         lines += [f"Counter calibration (copy kernel of {copy_mib} MiB read + {copy_mib} MiB written): "
                   f"FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {wf:.3f}" if ff and wf else
@@ -141,8 +188,11 @@ def main(argv=None):
     ap.add_argument("--title", default="")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--out")
+    ap.add_argument("--digest", action="store_true",
+                    help="record the digest of the kernel sources the profile was taken with")
     a = ap.parse_args(argv)
-    text = summarize(a.trace, a.fetch, a.write, a.copy_mib, a.title, a.command)
+    text = summarize(a.trace, a.fetch, a.write, a.copy_mib, a.title, a.command,
+                     kernel_source_digest() if a.digest else None)
     if a.out:
         with open(a.out, "w") as fh:
             fh.write(text)
