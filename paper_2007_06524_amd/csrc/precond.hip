@@ -587,21 +587,23 @@ __global__ __launch_bounds__(256) void k_gemm_16c(GemmArgs g) {
       u32x4 bfr[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) bfr[j] = *(const u32x4*)(sB + rdB[q] + j * 16 * BK);
-      u32x4 af[2][TM];
+      int aoff[TM];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         int u0 = kin + 32 * q - (jr + 16 * i);
         if (u0 < 0) u0 += N;
-        const int off = (u0 & 7) * NP8 + (u0 & ~7);
-        af[0][i] = *(const u32x4*)(cpy + off);
-        af[1][i] = *(const u32x4*)(cpy + 8 * NP8 + off);
+        aoff[i] = (u0 & 7) * NP8 + (u0 & ~7);
       }
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
+      for (int p = 0; p < 2; ++p) {  // hi, then lo plane
+        u32x4 af[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = *(const u32x4*)(cpy + p * 8 * NP8 + aoff[i]);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < TN; ++j) mfma(af[p][i], bfr[j], acc[i][j]);
+          for (int j = 0; j < TN; ++j) mfma(af[i], bfr[j], acc[i][j]);
+      }
     }
     lds_barrier();
   }
@@ -618,7 +620,7 @@ constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}}
 constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 0},  {128, 64, 64, 0},   {64, 128, 64, 0},
                                      {128, 128, 64, 0}, {128, 128, 32, 0},  {64, 128, 32, 0},
                                      {64, 128, 64, 1},  {128, 128, 64, 1},  {128, 128, 32, 1},
-                                     {128, 128, 128, 1}};
+                                     {32, 64, 32, 1}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
@@ -654,6 +656,8 @@ int run_gemm_f64(kp_context* ctx, GemmArgs g, int batch, int cfg, int stage) {
   return KP_OK;
 }
 
+// CIRC: both operands streamed (k_gemm_16) or the circulant operand built in
+// LDS (k_gemm_16c).
 template <int STAGE, int BM, int BN, int BK, bool CIRC, typename TO>
 void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
   dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
@@ -693,7 +697,7 @@ int resolve16(const GemmArgs& g, int batch, int cfg, int* order) {
   *order = cfg / kTiles16;
   int t = cfg % kTiles16;
   if (kCfg16[t][3] && !circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]))
-    t = t == 9 ? 3 : (t == 8 ? 4 : (t == 7 ? 3 : 2));
+    t = t == 9 ? 0 : (t == 8 ? 4 : (t == 7 ? 3 : 2));
   return t;
 }
 
@@ -720,7 +724,7 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
     case 6: launch16<STAGE, 64, 128, 64, true, TO>(ctx, g, batch, f16); break;
     case 7: launch16<STAGE, 128, 128, 64, true, TO>(ctx, g, batch, f16); break;
     case 8: launch16<STAGE, 128, 128, 32, true, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 128, 128, 128, true, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 32, 64, 32, true, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
