@@ -207,9 +207,13 @@ int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors
  * scratch operands of the preconditioner's size) and keeps the fastest per
  * stage for later applies.  table (host, may be NULL) receives up to cap
  * entries {stage 0..2 (contracting i3, i2, (k,i1)), tile rows, tile columns,
- * K tile, block order, circulant operand (1: built in LDS from the
- * circulants' first columns, only the data operand is streamed; 0: both
- * operands streamed), average ms}; *count the number of configurations timed.  Block order 0 walks the column tiles of
+ * K tile, block order, kernel (0: both operands streamed through LDS;
+ * 1: circulant operand built in LDS from the circulants' first columns, only
+ * the data operand streamed; 2: as 1, the data operand streamed by each wave
+ * straight into registers; a configuration whose kernel cannot run the stage
+ * runs as the nearest one that can, and reports that one's kernel), average
+ * ms}; *count the number of configurations timed.  Block order 0 walks the
+ * column tiles of
  * the data operand fastest; order 1 gives all row tiles of one column tile to
  * blocks on the same XCD (one L2), so that column tile is read from HBM once.
  * Synchronizes the stream. */

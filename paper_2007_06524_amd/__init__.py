@@ -180,8 +180,10 @@ class Precond:
     def autotune(self, reps: int = 5):
         """Time the tile configurations of the three GEMM stages and keep the fastest.
 
-        Returns [(stage, bm, bn, bk, order, circ, ms), ...] for every configuration timed."""
-        cap = 64
+        Returns [(stage, bm, bn, bk, order, kernel, ms), ...] for every configuration
+        timed; kernel 0 streams both operands, 1 builds the circulant operand in LDS,
+        2 streams the data operand per wave."""
+        cap = 256
         table = (_lib.TileTiming * cap)()
         n = C.c_int(0)
         check(load().kp_precond_autotune(self.ctx.handle, self.handle, int(reps), table, cap, C.byref(n)))

@@ -611,16 +611,207 @@ __global__ __launch_bounds__(256) void k_gemm_16c(GemmArgs g) {
   epilogue16<BM, BN, F16, TO>(g, acc, smem, C, m0, n0, bo, bi, true);
 }
 
+// Wave-streamed product for large circulant stages.  The data operand is the
+// first MFMA operand and goes from global memory straight into registers: each
+// wave owns 32 columns of the result and keeps the next four 32-wide K steps
+// of them in flight (a register ring, no LDS and no barrier in the K loop).
+// The circulant is the second MFMA operand, read from the shifted copies in
+// LDS.  A wave covers 128 circulant rows as eight 16-row fragments; fragment c
+// at K step q (inside one circulant) starts at (32 q - 16 c - row) mod N, which
+// depends on 2q - c only (a Toeplitz matrix), so going from step q to q + 1
+// keeps six of the eight fragments and reads two new ones (hi and lo planes).
+// The MFMA result of a lane is four consecutive data columns of one circulant
+// row; the data fragments' rows are assigned to columns so that each lane ends
+// with eight consecutive columns and writes them as one (16-bit) or two
+// (float) 16-byte stores.  Block: WAVES_M x (4 / WAVES_M) waves.  Stage (iii)
+// runs over R circulants along K: two LDS buffers, the next circulant loaded
+// while the current one is used, one barrier per circulant.
+// Requires: N a multiple of 256, every tile interior (checked by wave_ok).
+template <int STAGE, int TMC, int TND, int WAVES_M, bool F16, typename TO>
+__global__ __launch_bounds__(256, 2) void k_gemm_16w(GemmArgs g) {
+  static_assert((TMC == 4 || TMC == 8) && TND % 2 == 0, "wave tile");
+  constexpr int WM = 16 * TMC, WN = 16 * TND;
+  constexpr int WAVES_N = 4 / WAVES_M;
+  constexpr int BM = WAVES_M * WM, BN = WAVES_N * WN;
+  constexpr int D = 4;  // K steps in flight per wave (a multiple of 4, dividing N / 32)
+  const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
+  if (g.done && g.done[(long long)bo * g.done_stride]) return;
+  extern __shared__ __attribute__((aligned(16))) bf16_t cpy[];  // [buffer][2][8][N + 8]
+  __shared__ double red[20];
+  const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
+  TO* __restrict__ C = (TO*)g.C + (long long)bo * g.sCb;
+  int mt, nt;
+  tile_of(g.M / BM, g.order, mt, nt);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / WAVES_N, wn = wid - (wid / WAVES_N) * WAVES_N;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int N = g.cn, NP8 = N + 8, CPY = 16 * NP8;
+  const int QC = N / 32, QT = g.K / 32;  // K steps per circulant / in total
+
+  // Data rows of this lane: fragment j, MFMA row l16 -> column
+  // nb + 4 TND (l16 / 4) + 4 j + l16 % 4, K run 8 kg .. 8 kg + 7 of each step.
+  const int nb = n0 + wn * WN;
+  const bf16_t* __restrict__ bp[TND];
+#pragma unroll
+  for (int j = 0; j < TND; ++j)
+    bp[j] = B + (long long)(nb + 4 * TND * (l16 >> 2) + 4 * j + (l16 & 3)) * g.ldb + 8 * kg;
+  u32x4 rb[D][TND];
+  auto load = [&](int slot, int q) {
+#pragma unroll
+    for (int j = 0; j < TND; ++j) rb[slot][j] = *(const u32x4*)(bp[j] + 32 * q);
+  };
+#pragma unroll
+  for (int s = 0; s < D; ++s) load(s, s);  // QT >= 8
+
+  // Copies of circulant ci into LDS buffer b.
+  auto fill = [&](int ci, int b) {
+    const u32x4* __restrict__ src = (const u32x4*)(g.circ + (long long)ci * CPY);
+    u32x4* dst = (u32x4*)(cpy + b * CPY);
+    for (int v = tid; v < 2 * NP8; v += 256) dst[v] = src[v];
+  };
+  const int nc = g.cmode == 2 ? QT / QC : 1;  // circulants along K
+  fill(g.cmode == 0 ? m0 / N : (g.cmode == 1 ? bi : 0), 0);
+  if (nc > 1) fill(1, 1);
+  __syncthreads();
+
+  // Circulant fragment s = 2 q - c (in ring slot s mod TMC): copy offset of
+  // u = (16 s + base) mod N, base = (8 kg - row) mod N.
+  const int mr = m0 % N + wm * WM + l16;
+  int base = 8 * kg - mr;
+  base = base < 0 ? base + N : base;
+  u32x4 ca[TMC][2];
+  const bf16_t* cb = cpy;
+  auto frag = [&](int slot, int s) {
+    int u = 16 * s + base;
+    u = u < 0 ? u + N : (u >= N ? u - N : u);
+    const bf16_t* p = cb + (u & 7) * NP8 + (u & ~7);
+    ca[slot][0] = *(const u32x4*)p;
+    ca[slot][1] = *(const u32x4*)(p + 8 * NP8);
+  };
+  auto mfma = [&](const u32x4& a, const u32x4& b, flt4& c) {
+    if constexpr (F16)
+      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    else
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  };
+  flt4 acc[TMC][TND];
+#pragma unroll
+  for (int c = 0; c < TMC; ++c)
+#pragma unroll
+    for (int j = 0; j < TND; ++j) acc[c][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+  for (int q0 = 0; q0 < QT; q0 += D) {
+    const int qc = q0 - (q0 / QC) * QC;  // step inside the current circulant
+    if (qc == 0) {
+      const int cc = q0 / QC;
+      if (cc > 0) {
+        // Everyone is done with circulant cc - 1 (its buffer is free) and the
+        // copies of cc (loaded at the previous boundary) are visible.
+        __syncthreads();
+        if (cc + 1 < nc) fill(cc + 1, (cc + 1) & 1);
+      }
+      cb = cpy + (cc & 1) * CPY;
+#pragma unroll
+      for (int c = 0; c < TMC; ++c) frag((TMC - c) & (TMC - 1), -c);
+    }
+#pragma unroll
+    for (int dq = 0; dq < D; ++dq) {
+      const int q = q0 + dq, qp = qc + dq;
+      if (dq > 0 || qc > 0) {  // two new fragments: s = 2 qp - 1 and 2 qp
+        frag((2 * dq + TMC - 1) & (TMC - 1), 2 * qp - 1);
+        frag((2 * dq) & (TMC - 1), 2 * qp);
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int c = 0; c < TMC; ++c)
+#pragma unroll
+          for (int j = 0; j < TND; ++j) mfma(rb[dq][j], ca[(2 * dq - c + TMC) & (TMC - 1)][p], acc[c][j]);
+      if (q + D < QT) load(dq, q + D);
+    }
+  }
+
+  // Epilogue: lane (l16, kg) holds rows m = m0 + wm WM + 16 c + l16 and the
+  // 4 TND columns nb + 4 TND kg .. (acc[c][j][v] at column + 4 j + v).
+  const float oscale = g.out_div ? (float)(1.0 / g.out_div[(long long)bo * g.div_stride]) : 1.0f;
+  const int ncol = nb + 4 * TND * kg;
+  const int run_q = ncol / g.om.nd;
+  const long long col = (long long)run_q * g.om.sn1 + (ncol - run_q * g.om.nd) + (long long)bi * g.om.sb;
+  constexpr bool DOTS = sizeof(TO) == 4;
+  const bool dots = DOTS && g.dpart;
+  double dacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < TMC; ++c) {
+    const long long idx = (long long)(m0 + wm * WM + 16 * c + l16) * g.om.sm + col;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int j = 0; j < TND; ++j) {
+        const flt4 z = acc[c][j] * oscale;
+        *(flt4*)(C + idx + 4 * j) = z;
+        if (dots) {
+          const flt4 r = *(const flt4*)(g.dr + (long long)bo * g.sCb + idx + 4 * j);
+          const flt4 qv = g.dq ? *(const flt4*)(g.dq + (long long)bo * g.sCb + idx + 4 * j)
+                               : flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double zd = z[e], rd = r[e], qd = qv[e];
+            dacc[0] += rd * zd;
+            dacc[1] += qd * zd;
+            dacc[2] += zd;
+            dacc[3] += rd;
+            dacc[4] += qd;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < TND / 2; ++h) {  // eight columns per 16-byte store
+        u32x4 w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          w[e] = (uint32_t)cvt_out<TO, F16>(acc[c][2 * h + (e >> 1)][2 * (e & 1)] * oscale) |
+                 ((uint32_t)cvt_out<TO, F16>(acc[c][2 * h + (e >> 1)][2 * (e & 1) + 1] * oscale) << 16);
+        *(u32x4*)(C + idx + 8 * h) = w;
+      }
+    }
+  }
+  if constexpr (DOTS) {
+    if (dots) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        double x = dacc[v];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[v * 4 + wid] = x;
+      }
+      __syncthreads();
+      if (tid < 5) {
+        const int G = gridDim.x;
+        g.dpart[((long long)bo * 5 + tid) * G + blockIdx.x] =
+            (red[tid * 4 + 0] + red[tid * 4 + 1]) + (red[tid * 4 + 2] + red[tid * 4 + 3]);
+      }
+    }
+  }
+}
+
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Tile configurations (block rows x block columns [x K tile for 16-bit]).  The
 // autotuner times them per stage; without tuning a size heuristic picks one.
 constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
-// 16-bit: {BM, BN, BK, circulant operand built in LDS (k_gemm_16c)}.
+// 16-bit: {BM, BN, BK, kernel}: kernel 0 streams both operands (k_gemm_16),
+// 1 builds the circulant operand in LDS (k_gemm_16c), 2 streams the data
+// operand per wave (k_gemm_16w; BK is the number of 16-row circulant
+// fragments per wave, so the block has BM / (16 BK) waves along its rows and
+// the rest of its four waves along its columns).
 constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 0},  {128, 64, 64, 0},   {64, 128, 64, 0},
                                      {128, 128, 64, 0}, {128, 128, 32, 0},  {64, 128, 32, 0},
                                      {64, 128, 64, 1},  {128, 128, 64, 1},  {128, 128, 32, 1},
-                                     {32, 64, 32, 1}};
+                                     {32, 64, 32, 1},   {128, 128, 8, 2},   {256, 64, 8, 2},
+                                     {64, 256, 4, 2},   {128, 128, 4, 2},   {256, 64, 4, 2},
+                                     {128, 64, 4, 2}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
@@ -656,12 +847,19 @@ int run_gemm_f64(kp_context* ctx, GemmArgs g, int batch, int cfg, int stage) {
   return KP_OK;
 }
 
-// CIRC: both operands streamed (k_gemm_16) or the circulant operand built in
-// LDS (k_gemm_16c).
-template <int STAGE, int BM, int BN, int BK, bool CIRC, typename TO>
+// KIND: both operands streamed (k_gemm_16), the circulant operand built in
+// LDS (k_gemm_16c) or the data operand streamed per wave (k_gemm_16w).
+template <int STAGE, int BM, int BN, int BK, int KIND, typename TO>
 void launch16(kp_context* ctx, const GemmArgs& g, int batch, bool f16) {
   dim3 grid(((g.Nn + BN - 1) / BN) * ((g.M + BM - 1) / BM), 1, batch);
-  if constexpr (CIRC) {
+  if constexpr (KIND == 2) {  // BK: circulant fragments per wave (TMC); wave tile 16 TMC x (1024 / TMC / 4 waves)
+    constexpr int TMC = BK, WM = 16 * TMC, WAVES_M = BM / WM, TND = BN * WAVES_M / 64;
+    static_assert(WAVES_M >= 1 && 4 % WAVES_M == 0 && TND >= 2, "wave tile");
+    const int nbuf = (g.cmode == 2 && g.K > g.cn) ? 2 : 1;
+    const size_t shm = (size_t)nbuf * 16 * (g.cn + 8) * sizeof(bf16_t);
+    if (f16) hipLaunchKernelGGL((k_gemm_16w<STAGE, TMC, TND, WAVES_M, true, TO>), grid, dim3(256), shm, ctx->stream, g);
+    else hipLaunchKernelGGL((k_gemm_16w<STAGE, TMC, TND, WAVES_M, false, TO>), grid, dim3(256), shm, ctx->stream, g);
+  } else if constexpr (KIND == 1) {
     const size_t shm = (size_t)16 * (g.cn + 8) * sizeof(bf16_t);
     if (f16) hipLaunchKernelGGL((k_gemm_16c<STAGE, BM, BN, BK, true, TO>), grid, dim3(256), shm, ctx->stream, g);
     else hipLaunchKernelGGL((k_gemm_16c<STAGE, BM, BN, BK, false, TO>), grid, dim3(256), shm, ctx->stream, g);
@@ -689,15 +887,32 @@ bool circ_ok(const GemmArgs& g, int BM, int BN, int BK) {
          g.Nn % BN == 0 && g.K % BK == 0 && (g.cmode != 0 || g.cn % BM == 0) &&
          (g.cmode == 0 || g.M == g.cn);
 }
+// Can k_gemm_16w run it with block tile BM x BN?  As circ_ok, plus N a
+// multiple of 256 (eight K steps per ring turn inside one circulant), K whole
+// circulants, and 16-byte aligned runs of eight columns in the output (and in
+// r, q for the fused dot products).
+bool wave_ok(const GemmArgs& g, int BM, int BN) {
+  const bool out = g.om.sn2 == 1 && (g.om.nd == INT_MAX || g.om.nd % 64 == 0) && g.om.sm % 8 == 0 && g.om.sn1 % 8 == 0 &&
+                   g.om.sb % 8 == 0 && g.sCb % 8 == 0 && aligned16(g.C);
+  const bool dots = !g.dpart || (aligned16(g.dr) && (!g.dq || aligned16(g.dq)));
+  return g.circ && g.a_lo && vec_ok(g) && g.cn % 256 == 0 && g.M % BM == 0 && g.Nn % BN == 0 &&
+         g.K % g.cn == 0 && (g.cmode != 0 || g.cn % BM == 0) && (g.cmode == 0 || g.M == g.cn) &&
+         (g.cmode == 2 || g.K == g.cn) && out && dots;
+}
+bool tile_ok(const GemmArgs& g, int t) {
+  if (kCfg16[t][3] == 2) return wave_ok(g, kCfg16[t][0], kCfg16[t][1]);
+  if (kCfg16[t][3] == 1) return circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]);
+  return true;
+}
 // The tile configuration a 16-bit launch uses: cfg = tile + kTiles16 * order
-// (out of range: the size heuristic); a circulant-operand tile that cannot run
-// this product becomes the same (or nearest) tile through registers.
+// (out of range: the size heuristic); a tile whose kernel cannot run this
+// product becomes the nearest one that can (circulant in LDS, else streamed).
 int resolve16(const GemmArgs& g, int batch, int cfg, int* order) {
   if (cfg < 0 || cfg >= 2 * kTiles16) cfg = heuristic16(g, batch);
   *order = cfg / kTiles16;
   int t = cfg % kTiles16;
-  if (kCfg16[t][3] && !circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]))
-    t = t == 9 ? 0 : (t == 8 ? 4 : (t == 7 ? 3 : 2));
+  if (!tile_ok(g, t) && kCfg16[t][3] == 2) t = 7;
+  if (!tile_ok(g, t)) t = t == 9 ? 0 : (t == 8 ? 4 : (t == 7 ? 3 : 2));
   return t;
 }
 
@@ -715,16 +930,22 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
   g.vec = vec_ok(g);
   const int t = resolve16(g, batch, cfg, &g.order);
   switch (t) {
-    case 0: launch16<STAGE, 64, 64, 64, false, TO>(ctx, g, batch, f16); break;
-    case 1: launch16<STAGE, 128, 64, 64, false, TO>(ctx, g, batch, f16); break;
-    case 2: launch16<STAGE, 64, 128, 64, false, TO>(ctx, g, batch, f16); break;
-    case 3: launch16<STAGE, 128, 128, 64, false, TO>(ctx, g, batch, f16); break;
-    case 4: launch16<STAGE, 128, 128, 32, false, TO>(ctx, g, batch, f16); break;
-    case 5: launch16<STAGE, 64, 128, 32, false, TO>(ctx, g, batch, f16); break;
-    case 6: launch16<STAGE, 64, 128, 64, true, TO>(ctx, g, batch, f16); break;
-    case 7: launch16<STAGE, 128, 128, 64, true, TO>(ctx, g, batch, f16); break;
-    case 8: launch16<STAGE, 128, 128, 32, true, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 32, 64, 32, true, TO>(ctx, g, batch, f16); break;
+    case 0: launch16<STAGE, 64, 64, 64, 0, TO>(ctx, g, batch, f16); break;
+    case 1: launch16<STAGE, 128, 64, 64, 0, TO>(ctx, g, batch, f16); break;
+    case 2: launch16<STAGE, 64, 128, 64, 0, TO>(ctx, g, batch, f16); break;
+    case 3: launch16<STAGE, 128, 128, 64, 0, TO>(ctx, g, batch, f16); break;
+    case 4: launch16<STAGE, 128, 128, 32, 0, TO>(ctx, g, batch, f16); break;
+    case 5: launch16<STAGE, 64, 128, 32, 0, TO>(ctx, g, batch, f16); break;
+    case 6: launch16<STAGE, 64, 128, 64, 1, TO>(ctx, g, batch, f16); break;
+    case 7: launch16<STAGE, 128, 128, 64, 1, TO>(ctx, g, batch, f16); break;
+    case 8: launch16<STAGE, 128, 128, 32, 1, TO>(ctx, g, batch, f16); break;
+    case 9: launch16<STAGE, 32, 64, 32, 1, TO>(ctx, g, batch, f16); break;
+    case 10: launch16<STAGE, 128, 128, 8, 2, TO>(ctx, g, batch, f16); break;
+    case 11: launch16<STAGE, 256, 64, 8, 2, TO>(ctx, g, batch, f16); break;
+    case 12: launch16<STAGE, 64, 256, 4, 2, TO>(ctx, g, batch, f16); break;
+    case 13: launch16<STAGE, 128, 128, 4, 2, TO>(ctx, g, batch, f16); break;
+    case 14: launch16<STAGE, 256, 64, 4, 2, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 128, 64, 4, 2, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
@@ -880,7 +1101,8 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         e.bm = sixteen ? kCfg16[t][0] : kCfg64[t][0];
         e.bn = sixteen ? kCfg16[t][1] : kCfg64[t][1];
         e.bk = sixteen ? kCfg16[t][2] : 16;
-        e.circ = sixteen && kCfg16[t][3] && circ_ok(g, kCfg16[t][0], kCfg16[t][1], kCfg16[t][2]);
+        int ord;
+        e.circ = sixteen ? kCfg16[resolve16(g, batch, c, &ord)][3] : 0;
         e.order = c / ntile;
         e.ms = avg;
       }

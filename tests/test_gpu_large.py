@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2007_06524_amd as kp  # noqa: E402
 from oracle import assembly as asm  # noqa: E402
-from workloads import config_cells, random_field  # noqa: E402
+from workloads import config_cells, even_factors, random_field  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -68,6 +68,29 @@ def check_sampled_apply(pc, N, R, seed):
     ref = sampled_apply(F, x, pts)
     got = np.array([z[p] for p in pts])
     assert np.abs(got - ref).max() <= 1e-2 * np.sqrt(np.mean(ref ** 2))
+
+
+def test_wave_kernels_n512(ctx):
+    """N = 512 (16 K steps per circulant, so the wave-streamed kernels keep their
+    fragment ring across two turns of their loop) with R = 2: sampled outputs of
+    the apply under the circulant-operand tiles, both block orders, against the
+    circulant definition."""
+    N, R = 512, 2
+    F = even_factors(N, R, seed=5120)
+    pc = kp.Precond(ctx, N, precision="mixed_bf16", factors=F)
+    x = random_field(N, seed=512)
+    g = np.random.default_rng(77)
+    pts = [tuple(int(v) for v in g.integers(0, N, 3)) for _ in range(6)] + [(0, 0, 0), (N - 1, N - 1, N - 1)]
+    ref = sampled_apply(F, x, pts)
+    xd = torch.from_numpy(x).cuda()
+    for t in (7, 10, 11):
+        for order in (0, 1):
+            c = t + 12 * order
+            pc.tiles = (c, c, c)
+            z = pc.apply(xd)
+            got = np.array([float(z[p]) for p in pts])
+            assert np.abs(got - ref).max() <= 1e-2 * np.sqrt(np.mean(ref ** 2)), (t, order)
+    pc.free()
 
 
 def ahom_bounds_ok(A, cells):
