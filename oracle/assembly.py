@@ -34,21 +34,54 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def voxel_field(cells: np.ndarray, n0: int) -> np.ndarray:
-    """Coefficient value on every voxel: a_vox(v) = a_cell(floor(v / n0))."""
+def inclusion_range(n0: int, k: int) -> tuple[int, int]:
+    """Voxel range [lo, lo + k) of the centred sub-cell inside a cell of n0 voxels.
+
+    Section 3.1: the unit cell G_s contains the sub-cell S_s of edge 2 alpha / L
+    = k h (k = 2 alpha n0, an even number of grid intervals up to n0) with the
+    same centre, so S_s covers the voxels (n0 - k)/2 .. (n0 + k)/2 - 1 of the
+    cell along every axis.
+    """
+    if not (0 < k <= n0) or (n0 - k) % 2:
+        raise ValueError(f"sub-cell of {k} voxels does not centre in a cell of {n0}")
+    lo = (n0 - k) // 2
+    return lo, lo + k
+
+
+def voxel_field(cells: np.ndarray, n0: int, k: int | None = None,
+                background: float | None = None) -> np.ndarray:
+    """Coefficient value on every voxel.
+
+    Full cells (k None or n0): a_vox(v) = a_cell(floor(v / n0)).  Sub-cell
+    inclusions (Section 3.1, k < n0): a voxel takes its cell's value when it
+    lies in the centred sub-cell (every local coordinate v mod n0 in
+    inclusion_range) and the background value elsewhere; a cell whose value
+    equals the background is an unperturbed cell (the paper's binary model
+    a = 1 on the union of the perturbed sub-cells and lambda elsewhere).
+    """
     a = np.asarray(cells, dtype=np.float64)
     for ax in range(a.ndim):
         a = np.repeat(a, n0, axis=ax)
-    return a
+    if k is None or k == n0:
+        return a
+    if background is None or not background > 0:
+        raise ValueError("sub-cell inclusions need a positive background value")
+    lo, hi = inclusion_range(n0, k)
+    loc = np.arange(a.shape[0]) % n0
+    inside = (loc >= lo) & (loc < hi)
+    mask = inside[:, None, None] & inside[None, :, None] & inside[None, None, :]
+    return np.where(mask, a, float(background))
 
 
-def edge_weights(cells: np.ndarray, n0: int) -> np.ndarray:
+def edge_weights(cells: np.ndarray, n0: int, k: int | None = None,
+                 background: float | None = None) -> np.ndarray:
     """Edge weights w[l][p] of the edge (p, p + e_l), shape (3, N, N, N).
 
     Along axis l the edge lies in voxel layer p_l; on each transverse axis t
     the four voxels sharing it have coordinate p_t - 1 or p_t (mod N).
+    (k, background: sub-cell inclusions, see voxel_field.)
     """
-    A = voxel_field(cells, n0)
+    A = voxel_field(cells, n0, k, background)
     w = np.empty((3,) + A.shape)
     for l in range(3):
         t1, t2 = [t for t in range(3) if t != l]
@@ -82,7 +115,8 @@ def corrector_rhs(w: np.ndarray, i: int) -> np.ndarray:
     return h * (w[l] - np.roll(w[l], 1, axis=l))
 
 
-def fem_rhs_quadrature(cells: np.ndarray, n0: int, i: int) -> np.ndarray:
+def fem_rhs_quadrature(cells: np.ndarray, n0: int, i: int, k: int | None = None,
+                       background: float | None = None) -> np.ndarray:
     """Corrector right-hand side from the Galerkin definition, by brute force.
 
     eq. FEM_discr_RHS: f_{mu,i} = -int_Omega a(x) dpsi_mu/dx_i dx with
@@ -92,7 +126,7 @@ def fem_rhs_quadrature(cells: np.ndarray, n0: int, i: int) -> np.ndarray:
     -a_v * (+-h^2/4) to each corner.  Returned divided by h (K = A / h).
     Pure-Python loop: tiny grids only.
     """
-    A = voxel_field(cells, n0)
+    A = voxel_field(cells, n0, k, background)
     N = A.shape[0]
     h = 1.0 / N
     l = i - 1
@@ -110,13 +144,14 @@ def fem_rhs_quadrature(cells: np.ndarray, n0: int, i: int) -> np.ndarray:
     return f / h
 
 
-def nodal_coefficient(cells: np.ndarray, n0: int) -> np.ndarray:
+def nodal_coefficient(cells: np.ndarray, n0: int, k: int | None = None,
+                      background: float | None = None) -> np.ndarray:
     """Mean of the coefficient over the 2^d voxels around each node.
 
     Section 3.3 (Fig. Check_coef): for a binary inclusion this is 1 inside,
     1/2 on a face, 1/4 on an exterior edge (a corner in 2D), and so on.
     """
-    A = voxel_field(cells, n0)
+    A = voxel_field(cells, n0, k, background)
     s = np.zeros_like(A)
     for c in range(8):
         shifted = A
@@ -182,6 +217,51 @@ def kron_stiffness(cells: np.ndarray, n0: int) -> sp.csr_matrix:
                 Q1, Q2, Q3 = (embed(Q, c * n0, N) for c in (c1, c2, c3))
                 I1, I2, I3 = (embed(I, c * n0, N) for c in (c1, c2, c3))
                 K = K + a * (sp.kron(sp.kron(Q1, I2), I3)
+                             + sp.kron(sp.kron(I1, Q2), I3)
+                             + sp.kron(sp.kron(I1, I2), Q3))
+    return K.tocsr()
+
+
+def periodic_laplacian_block(N: int) -> sp.csr_matrix:
+    """1D periodic Laplacian on N nodes (the positive semidefinite -Delta_{1,P}
+    of Section 3.2: 2 on the diagonal, -1 on the two cyclic off-diagonals)."""
+    rows, cols, vals = [], [], []
+    for a in range(N):
+        for b, v in ((a, 2.0), ((a + 1) % N, -1.0), ((a - 1) % N, -1.0)):
+            rows.append(a)
+            cols.append(b)
+            vals.append(v)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def kron_stiffness_inclusions(cells: np.ndarray, n0: int, k: int, background: float) -> sp.csr_matrix:
+    """Paper-literal stiffness with centred sub-cell inclusions, 3D, sparse.
+
+    The background value b everywhere is b times the periodic Laplacian as a
+    Kronecker sum of 1D periodic Laplacians with identities (eq. Lapl_Kron3);
+    every cell c then adds (a_c - b) times the Kronecker sum of the Neumann
+    block and the half identity of size k + 1 (eq. As_Kron_d with the sub-cell
+    of Section 3.3 in place of the cell), embedded at the sub-cell's node
+    indices c n0 + lo .. c n0 + lo + k (mod N).  Tiny L only.
+    """
+    L = cells.shape[0]
+    N = n0 * L
+    lo, _ = inclusion_range(n0, k)
+    D = periodic_laplacian_block(N)
+    E = sp.identity(N, format="csr")
+    b = float(background)
+    K = b * (sp.kron(sp.kron(D, E), E) + sp.kron(sp.kron(E, D), E) + sp.kron(sp.kron(E, E), D))
+    Q = neumann_block(k + 1)
+    I = half_identity(k + 1)
+    for c1 in range(L):
+        for c2 in range(L):
+            for c3 in range(L):
+                d = float(cells[c1, c2, c3]) - b
+                if d == 0.0:
+                    continue
+                Q1, Q2, Q3 = (embed(Q, c * n0 + lo, N) for c in (c1, c2, c3))
+                I1, I2, I3 = (embed(I, c * n0 + lo, N) for c in (c1, c2, c3))
+                K = K + d * (sp.kron(sp.kron(Q1, I2), I3)
                              + sp.kron(sp.kron(I1, Q2), I3)
                              + sp.kron(sp.kron(I1, I2), Q3))
     return K.tocsr()

@@ -18,16 +18,18 @@ from __future__ import annotations
 
 import numpy as np
 
-from .assembly import corrector_rhs, edge_weights, stiffness_apply
+from .assembly import corrector_rhs, edge_weights, stiffness_apply, voxel_field
 from .fourier import apply_pinv_laplacian
 from .pcg import pcg
 
 
-def homogenized_matrix(cells, phis, fs):
+def homogenized_matrix(a, phis, fs):
+    """a: the cell values (full cells) or the voxel field (any coefficient); only
+    its mean enters, the exact integral of the coefficient over the cube."""
     N = phis[0].shape[0]
     h = 1.0 / N
     A = np.zeros((3, 3))
-    m = float(np.mean(cells))
+    m = float(np.mean(a))
     for i in range(3):
         for j in range(3):
             A[i, j] = (m if i == j else 0.0) - h * float(np.vdot(phis[i], fs[j]))
@@ -55,12 +57,29 @@ def homogenized_energy(w, phi, i):
     return h ** 3 * s
 
 
-def solve_correctors(cells, n0, tol=1e-12, maxit=5000):
-    """Assemble, solve the three correctors with the exact preconditioner, form a_hom."""
-    w = edge_weights(cells, n0)
+def solve_correctors(cells, n0, tol=1e-12, maxit=5000, k=None, background=None):
+    """Assemble, solve the three correctors with the exact preconditioner, form a_hom.
+    (k, background: centred sub-cell inclusions, see assembly.voxel_field.)"""
+    w = edge_weights(cells, n0, k, background)
     K = lambda u: stiffness_apply(w, u)
     fs = [corrector_rhs(w, i) for i in (1, 2, 3)]
     sols = [pcg(K, f, apply_pinv_laplacian, tol=tol, maxit=maxit) for f in fs]
     phis = [s["x"] for s in sols]
     return dict(w=w, fs=fs, phis=phis, solves=sols,
-                ahom=homogenized_matrix(cells, phis, fs))
+                ahom=homogenized_matrix(voxel_field(cells, n0, k, background), phis, fs))
+
+
+def empirical_statistics(ahoms):
+    """Empirical average and standard deviation over M realizations (Section 5.3).
+
+    eq. A_hom_Empir: the mean of the M matrices; the standard deviation uses the
+    M - 1 normalization of the paper's sigma_L^M, entry by entry.
+    ahoms: (M, 3, 3).  Returns (mean, std), each 3 x 3.
+    """
+    A = np.asarray(ahoms, dtype=np.float64)
+    M = A.shape[0]
+    if M < 2:
+        raise ValueError("the standard deviation needs at least two realizations")
+    mean = A.sum(axis=0) / M
+    std = np.sqrt(((A - mean) ** 2).sum(axis=0) / (M - 1))
+    return mean, std

@@ -122,3 +122,90 @@ def test_constant_coefficient_is_scaled_laplacian():
     w = asm.edge_weights(cells, 3)
     u = random_field(6, seed=1)
     np.testing.assert_allclose(asm.stiffness_apply(w, u), 3.5 * fo.laplacian_apply(u), atol=1e-12)
+
+
+# ---- centred sub-cell inclusions (Section 3.1; alpha = k / (2 n0)) ----------
+
+@pytest.mark.parametrize("L,n0,k", [(2, 4, 2), (3, 4, 2), (2, 6, 2), (2, 6, 4)])
+def test_inclusion_literal_equals_stencil(L, n0, k):
+    """Background periodic Laplacian (eq. Lapl_Kron3) plus the Kronecker sums of
+    the (k+1)-node sub-cell blocks (eq. As_Kron_d on S_s) equals the edge-average
+    stencil of the voxel field; the off-diagonal entries are the negated weights."""
+    b = 0.4
+    cells = cells_bernoulli(L, b, 1.0, 0.5, seed=300 + 10 * L + k)
+    cells[0, 0, 0], cells[-1, -1, -1] = 1.0, 2.5     # at least one perturbed cell, two values
+    N = n0 * L
+    K = asm.kron_stiffness_inclusions(cells, n0, k, b)
+    w = asm.edge_weights(cells, n0, k, b)
+    u = random_field(N, seed=9)
+    np.testing.assert_allclose(K @ u.reshape(-1), asm.stiffness_apply(w, u).reshape(-1),
+                               rtol=0, atol=1e-12 * np.abs(K).max() * np.abs(u).max())
+    idx = lambda p: (p[0] % N) * N * N + (p[1] % N) * N + (p[2] % N)
+    g = np.random.default_rng(1)
+    for _ in range(20):
+        p = tuple(int(v) for v in g.integers(0, N, 3))
+        for l in range(3):
+            q = list(p)
+            q[l] += 1
+            assert K[idx(p), idx(q)] == pytest.approx(-w[l][p], abs=1e-14)
+    assert abs(K - K.T).max() == 0.0
+    np.testing.assert_allclose(K @ np.ones(N ** 3), 0.0, atol=1e-12)
+
+
+def test_inclusion_full_subcell_is_the_cell():
+    """k = n0 (alpha = 1/2): the sub-cell is the cell, whatever the background."""
+    cells = cells_uniform(2, 1.0, 10.0, seed=41)
+    np.testing.assert_array_equal(asm.voxel_field(cells, 4, 4, 0.3), asm.voxel_field(cells, 4))
+    K0 = asm.kron_stiffness(cells, 4)
+    for b in (0.3, 7.0):
+        Kb = asm.kron_stiffness_inclusions(cells, 4, 4, b)
+        assert abs(Kb - K0).max() <= 1e-12 * abs(K0).max()
+
+
+def test_inclusion_range_and_voxel_mean():
+    """The sub-cell is centred (k voxels per edge, (n0 - k)/2 on either side) and the
+    voxel mean is b + (k/n0)^3 (mean(a_cell) - b)."""
+    assert asm.inclusion_range(4, 2) == (1, 3) and asm.inclusion_range(8, 4) == (2, 6)
+    for bad in ((4, 3), (4, 0), (4, 6)):
+        with pytest.raises(ValueError):
+            asm.inclusion_range(*bad)
+    cells = cells_uniform(3, 1.0, 10.0, seed=42)
+    for n0, k in ((4, 2), (8, 4), (8, 2), (6, 4)):
+        A = asm.voxel_field(cells, n0, k, 0.4)
+        assert A.mean() == pytest.approx(0.4 + (k / n0) ** 3 * (cells.mean() - 0.4), rel=1e-13)
+        lo, hi = asm.inclusion_range(n0, k)
+        # a voxel of cell (1,2,0) at local (lo, hi-1, lo) is inside, at (lo-1, lo, lo) outside
+        assert A[n0 + lo, 2 * n0 + hi - 1, lo] == cells[1, 2, 0]
+        assert A[n0 + lo - 1, 2 * n0 + lo, lo] == 0.4
+
+
+def test_inclusion_rhs_equals_galerkin_definition():
+    """The corrector right-hand side of the voxel field equals the Galerkin
+    integral of eq. FEM_discr_RHS (brute force over voxels) with inclusions."""
+    cells = cells_uniform(2, 1.0, 10.0, seed=43)
+    w = asm.edge_weights(cells, 4, 2, 0.4)
+    for i in (1, 2, 3):
+        np.testing.assert_allclose(asm.corrector_rhs(w, i), asm.fem_rhs_quadrature(cells, 4, i, 2, 0.4),
+                                   rtol=0, atol=1e-14)
+
+
+def test_inclusion_nodal_values_fig_check_coef():
+    """Fig. Check_coef for a sub-cell inclusion: on the mid-plane of a single
+    perturbed sub-cell (k = 2 in n0 = 4) the nodal coefficient in excess of the
+    background is 1 inside, 1/2 on the interface, 1/4 at an exterior corner."""
+    vals = {}
+    with open(os.path.join(GOLDEN, "nodal_weights_2d.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                key, v = line.split()
+                vals[key] = float(v)
+    b = 0.25
+    cells = np.full((2, 2, 2), b)
+    cells[0, 0, 0] = b + 1.0
+    nod = asm.nodal_coefficient(cells, 4, 2, b)[:, :, 2] - b    # sub-cell voxels 1..2, nodes 1..3
+    assert nod[2, 2] == vals["interior"]
+    for c in [(1, 2), (3, 2), (2, 1), (2, 3)]:
+        assert nod[c] == vals["interface"]
+    for c in [(1, 1), (1, 3), (3, 1), (3, 3)]:
+        assert nod[c] == vals["exterior_corner"]
+    assert nod[0, 0] == 0.0 and nod[5, 5] == 0.0

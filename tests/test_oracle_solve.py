@@ -183,3 +183,44 @@ def test_lowrank_and_exact_preconditioner_same_solution():
     a = pcg(K, f, fo.apply_pinv_laplacian, tol=1e-12)
     b = pcg(K, f, lambda r: lr.kron_apply(F, r), tol=1e-12)
     np.testing.assert_allclose(a["x"], b["x"], atol=1e-10 * np.abs(a["x"]).max())
+
+
+def test_inclusion_bounds_and_forms():
+    """Sub-cell inclusions (alpha = 1/4, binary {1, lambda = 0.4}, the paper's
+    Fig. Emp_a12_M20 setting): the corrector system still satisfies the
+    harmonic / arithmetic bounds of the voxel field, the flux form equals the
+    linear form, and the energy form equals the diagonal at the solution."""
+    b = 0.4
+    cells = cells_bernoulli(3, b, 1.0, 0.5, seed=61)
+    res = solve_correctors(cells, 4, tol=1e-12, k=2, background=b)
+    A = res["ahom"]
+    vox = asm.voxel_field(cells, 4, 2, b)
+    harm, arith = 1.0 / np.mean(1.0 / vox), vox.mean()
+    for i in range(3):
+        assert harm - 1e-12 <= A[i, i] <= arith + 1e-12
+        assert homogenized_energy(res["w"], res["phis"][i], i + 1) == pytest.approx(A[i, i], rel=1e-9)
+    np.testing.assert_allclose(homogenized_flux(res["w"], res["phis"]), A, atol=1e-12)
+    np.testing.assert_allclose(A, A.T, atol=1e-10)
+
+
+def test_empirical_statistics():
+    """eq. A_hom_Empir and the M - 1 standard deviation: identical realizations give
+    the value itself and zero spread; scaling every realization scales both; the
+    entries equal numpy's mean and ddof = 1 standard deviation; order does not matter."""
+    from oracle.homogenize import empirical_statistics
+    g = np.random.default_rng(5)
+    A = g.random((7, 3, 3))
+    mean, std = empirical_statistics(A)
+    np.testing.assert_allclose(mean, A.mean(axis=0), rtol=1e-15)
+    np.testing.assert_allclose(std, A.std(axis=0, ddof=1), rtol=1e-13)
+    m2, s2 = empirical_statistics(3.0 * A[::-1])
+    np.testing.assert_allclose(m2, 3.0 * mean, rtol=1e-14)
+    np.testing.assert_allclose(s2, 3.0 * std, rtol=1e-13)
+    m3, s3 = empirical_statistics(np.stack([A[0]] * 4))
+    np.testing.assert_allclose(m3, A[0], rtol=1e-15)
+    assert np.all(s3 < 1e-15)
+    # two realizations: std = |a - b| / sqrt(2)
+    _, s4 = empirical_statistics(A[:2])
+    np.testing.assert_allclose(s4, np.abs(A[0] - A[1]) / np.sqrt(2.0), rtol=1e-13)
+    with pytest.raises(ValueError):
+        empirical_statistics(A[:1])
