@@ -149,6 +149,26 @@ int kp_context_read_timing(kp_context* ctx, double* ms, long long* launches);
 int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precision,
                 kp_coeff** out);
 
+/* Same, with the coefficient perturbed only on the centred sub-cell of every
+ * unit cell (Section 3.1: the sub-cell S_s of edge 2 alpha / L = incl * h,
+ * i.e. alpha = incl / (2 n0), centred in G_s; Section 3.3 assembles the
+ * stiffness from Neumann blocks of incl + 1 nodes on the sub-cells).
+ *   incl: voxels per sub-cell edge, 1 <= incl <= n0 with n0 - incl even; the
+ *         voxels (n0 - incl)/2 .. (n0 + incl)/2 - 1 of a cell along every axis
+ *         form its sub-cell.  incl = n0 is setup_coeff.
+ *   background: coefficient everywhere outside the sub-cells (finite, > 0;
+ *         ignored when incl = n0).  A cell whose value equals the background
+ *         is an unperturbed cell: the paper's binary model is a_cell in
+ *         {1, lambda} with background lambda.
+ * A voxel inside a sub-cell takes the cell's value, any other the background;
+ * the edge weights are the voxel means as above.  The homogenized matrix uses
+ * the exact mean of this coefficient, background + (incl/n0)^3 (mean(a_cell)
+ * - background).  kp_coeff_update keeps incl and background.  Errors as
+ * setup_coeff, and KP_ERR_ARG for a sub-cell that does not centre or a bad
+ * background. */
+int setup_coeff_inclusions(kp_context* ctx, int L, int n0, int incl, double background,
+                           const double* a_cell, int precision, kp_coeff** out);
+
 /* Copy the assembled fields into caller device buffers (either may be NULL):
  *   w_dev: 3*N^3 doubles [l][i1][i2][i3];  f_dev: 3*N^3 doubles [i-1][i1][i2][i3]. */
 int kp_coeff_fields(kp_context* ctx, const kp_coeff* coeff, double* w_dev, double* f_dev);

@@ -109,9 +109,13 @@ def _close_all():
 
 
 class Coeff:
-    """An assembled coefficient realization (setup_coeff): weights and correctors' RHS."""
+    """An assembled coefficient realization (setup_coeff): weights and correctors' RHS.
 
-    def __init__(self, ctx: Context, cells: np.ndarray, n0: int, precision="fp64"):
+    inclusion, background: the cell value only on the centred sub-cell of
+    `inclusion` voxels per edge, `background` elsewhere (setup_coeff_inclusions)."""
+
+    def __init__(self, ctx: Context, cells: np.ndarray, n0: int, precision="fp64",
+                 inclusion: int | None = None, background: float | None = None):
         cells = np.ascontiguousarray(cells, dtype=np.float64)
         if cells.ndim != 3 or len(set(cells.shape)) != 1:
             raise ValueError("cells must be an (L, L, L) array")
@@ -119,9 +123,12 @@ class Coeff:
         self.L = cells.shape[0]
         self.n0 = int(n0)
         self.precision = _precision(precision)
+        self.inclusion = self.n0 if inclusion is None else int(inclusion)
+        self.background = 0.0 if background is None else float(background)
         h = C.c_void_p()
-        check(load().setup_coeff(ctx.handle, self.L, self.n0,
-                                 cells.ctypes.data_as(C.POINTER(C.c_double)), self.precision, C.byref(h)))
+        check(load().setup_coeff_inclusions(ctx.handle, self.L, self.n0, self.inclusion, self.background,
+                                            cells.ctypes.data_as(C.POINTER(C.c_double)), self.precision,
+                                            C.byref(h)))
         self.handle = h
         self.N = self.L * self.n0
         ctx._owned.append(self)

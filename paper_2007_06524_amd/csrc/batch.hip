@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <vector>
 
 #include "kp_internal.h"
@@ -33,6 +34,7 @@ namespace {
 struct Group {
   const kp_precond* pc = nullptr;
   int N = 0, L = 0, n0 = 0;
+  CellGeom cg;  // the coefficient geometry shared by the group's realizations
   size_t n3 = 0;
   std::vector<int> inst;  // instance indices
   int nsys = 0;
@@ -109,10 +111,10 @@ int true_residual(kp_context* ctx, BatchState& B, Group& g, int gate, int fin_mo
   int np = 0;
   if (B.mixed) KP_TRY(launch_fold(ctx, g.x, g.x32, g.n3, g.s, g.bt, gate));
   if (B.mixed)
-    KP_TRY(launch_resid_f64_to_f32(ctx, g.x, g.c64, g.L, g.n0, g.fp, (float*)g.r, g.part, &np, g.s, g.N,
+    KP_TRY(launch_resid_f64_to_f32(ctx, g.x, g.c64, g.cg, g.fp, (float*)g.r, g.part, &np, g.s, g.N,
                                    g.bt, gate));
   else
-    KP_TRY(launch_stencil_f64(ctx, g.x, g.c64, g.L, g.n0, g.fp, (double*)g.r, g.part, &np, g.s, g.N, g.bt,
+    KP_TRY(launch_stencil_f64(ctx, g.x, g.c64, g.cg, g.fp, (double*)g.r, g.part, &np, g.s, g.N, g.bt,
                               gate));
   return fin(ctx, g, np, 1, fin_mode);
 }
@@ -120,13 +122,13 @@ int true_residual(kp_context* ctx, BatchState& B, Group& g, int gate, int fin_mo
 int iteration(kp_context* ctx, BatchState& B, Group& g) {
   int np = 0;
   if (B.mixed) {
-    KP_TRY(launch_stencil_f32(ctx, (const float*)g.p, g.c32, g.L, g.n0, (float*)g.q, g.part, &np, g.s, g.N,
+    KP_TRY(launch_stencil_f32(ctx, (const float*)g.p, g.c32, g.cg, (float*)g.q, g.part, &np, g.s, g.N,
                               g.bt));
     KP_TRY(fin(ctx, g, np, 1, FIN_ALPHA));
     KP_TRY(launch_update_xr<float>(ctx, g.x, g.x32, (const float*)g.p, (float*)g.r, (const float*)g.q, g.x16,
                                    B.fp16, g.s, g.part, &np, g.n3, g.bt));
   } else {
-    KP_TRY(launch_stencil_f64(ctx, (const double*)g.p, g.c64, g.L, g.n0, nullptr, (double*)g.q, g.part, &np,
+    KP_TRY(launch_stencil_f64(ctx, (const double*)g.p, g.c64, g.cg, nullptr, (double*)g.q, g.part, &np,
                               g.s, g.N, g.bt));
     KP_TRY(fin(ctx, g, np, 1, FIN_ALPHA));
     KP_TRY(launch_update_xr<double>(ctx, g.x, nullptr, (const double*)g.p, (double*)g.r, (const double*)g.q,
@@ -223,16 +225,19 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
   B.mixed = mixed;
   B.fp16 = preconds[0]->precision == KP_MIXED_FP16;
   {
-    std::map<std::pair<const kp_precond*, int>, int> gid;
+    // Group key: preconditioner, cell size and sub-cell geometry (incl, background).
+    std::map<std::tuple<const kp_precond*, int, int, double>, int> gid;
     for (int i = 0; i < n_inst; ++i) {
-      const auto key = std::make_pair(preconds[i], coeffs[i]->n0);
+      const kp_coeff* c = coeffs[i];
+      const auto key = std::make_tuple(preconds[i], c->n0, c->incl, c->incl < c->n0 ? c->bg : 0.0);
       auto it = gid.find(key);
       if (it == gid.end()) {
         it = gid.emplace(key, (int)B.groups.size()).first;
         B.groups.emplace_back();
         B.groups.back().pc = preconds[i];
-        B.groups.back().n0 = coeffs[i]->n0;
-        B.groups.back().L = coeffs[i]->L;
+        B.groups.back().n0 = c->n0;
+        B.groups.back().L = c->L;
+        B.groups.back().cg = geom_of(c);
       }
       B.groups[it->second].inst.push_back(i);
     }

@@ -22,10 +22,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // a_hom = delta_ij mean(a) - h <phi_i, f_j> from the partials of the nine dot
-// products and of the cell sum (eq. Ahom3_m_entry_comp).
+// products and of the cell sum (eq. Ahom3_m_entry_comp).  mean(a) is the
+// integral of the coefficient over the cube: the mean cell value, or with
+// sub-cell inclusions (frac = (k / n0)^3 of every cell carries its value)
+// bg + frac (mean cell value - bg).
 __global__ __launch_bounds__(256) void k_ahom_final(const double* __restrict__ partial, int nparts,
-                                                    double ncells, double h,
-                                                    double* __restrict__ out) {
+                                                    double ncells, double h, int sub, double frac,
+                                                    double bg, double* __restrict__ out) {
   __shared__ double tot[10];
   __shared__ double red[4];
   for (int v = 0; v < 10; ++v) {
@@ -39,7 +42,8 @@ __global__ __launch_bounds__(256) void k_ahom_final(const double* __restrict__ p
   }
   if (threadIdx.x < 9) {
     const int i = threadIdx.x / 3, j = threadIdx.x % 3;
-    const double mean = tot[9] / ncells;
+    const double mc = tot[9] / ncells;
+    const double mean = sub ? bg + frac * (mc - bg) : mc;
     out[threadIdx.x] = (i == j ? mean : 0.0) - h * tot[threadIdx.x];
   }
 }
@@ -293,8 +297,10 @@ int launch_ahom(kp_context* ctx, const kp_coeff* c, const double* const* phi, do
   const size_t nc = (size_t)c->L * c->L * c->L;
   int np = 0;
   KP_TRY(launch_multidot9(ctx, phi, c->f, n3, c->cells, nc, part, &np));
+  const CellGeom cg = geom_of(c);
+  const double fr = (double)c->incl / c->n0;
   hipLaunchKernelGGL(k_ahom_final, dim3(1), dim3(256), 0, ctx->stream, (const double*)part, np,
-                     (double)nc, 1.0 / c->N, out);
+                     (double)nc, 1.0 / c->N, (int)cg.sub(), fr * fr * fr, c->bg, out);
   KP_HIP(hipGetLastError());
   return KP_OK;
 }
@@ -403,13 +409,17 @@ int kp_coeff_update(kp_context* ctx, kp_coeff* c, const double* a_cell_dev) {
   return launch_assemble(ctx, c);
 }
 
-int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precision,
-                kp_coeff** out) {
+int setup_coeff_inclusions(kp_context* ctx, int L, int n0, int incl, double background,
+                           const double* a_cell, int precision, kp_coeff** out) {
   if (!ctx || !a_cell || !out) return fail(KP_ERR_ARG, "setup_coeff: NULL argument");
   *out = nullptr;
   if (!valid_precision(precision)) return fail(KP_ERR_ARG, "setup_coeff: bad precision %d", precision);
   if (L < 1 || n0 < 1 || (long long)L * n0 < 2 || (long long)L * n0 > 2048)
     return fail(KP_ERR_ARG, "setup_coeff: need L >= 1, n0 >= 1, 2 <= N = n0*L <= 2048");
+  if (incl < 1 || incl > n0 || (n0 - incl) % 2 != 0)
+    return fail(KP_ERR_ARG, "setup_coeff: a sub-cell of %d voxels does not centre in a cell of %d", incl, n0);
+  if (incl < n0 && (!std::isfinite(background) || !(background > 0.0)))
+    return fail(KP_ERR_ARG, "setup_coeff: background %g must be finite and > 0", background);
   const int N = L * n0;
   const size_t nc = (size_t)L * L * L;
   for (size_t i = 0; i < nc; ++i) {
@@ -422,6 +432,8 @@ int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precis
   c->L = L;
   c->n0 = n0;
   c->N = N;
+  c->incl = incl;
+  c->bg = incl < n0 ? background : 0.0;
   c->precision = precision;
   const size_t n3 = (size_t)N * N * N;
   int st;
@@ -444,6 +456,11 @@ int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precis
   }
   *out = c;
   return KP_OK;
+}
+
+int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precision,
+                kp_coeff** out) {
+  return setup_coeff_inclusions(ctx, L, n0, n0, 0.0, a_cell, precision, out);
 }
 
 int kp_coeff_size(const kp_coeff* c) { return c ? c->N : -1; }
@@ -480,13 +497,13 @@ int kp_stiffness_apply(kp_context* ctx, const kp_coeff* c, int precision, const 
   KP_TRY(ws_get(ctx, WS_PART, (size_t)kMaxPartials * 8 * sizeof(double), &part));
   int np = 0;
   if (precision == KP_FP64)
-    return launch_stencil_f64(ctx, p_dev, c->cells, c->L, c->n0, nullptr, q_dev, (double*)part, &np,
+    return launch_stencil_f64(ctx, p_dev, c->cells, geom_of(c), nullptr, q_dev, (double*)part, &np,
                               nullptr, N);
   void *p32, *q32;
   KP_TRY(ws_get(ctx, WS_R, n3 * sizeof(float), &p32));
   KP_TRY(ws_get(ctx, WS_Q, n3 * sizeof(float), &q32));
   KP_TRY(launch_cast_f64_f32(ctx, p_dev, (float*)p32, n3));
-  KP_TRY(launch_stencil_f32(ctx, (const float*)p32, c->cells32, c->L, c->n0, (float*)q32, (double*)part,
+  KP_TRY(launch_stencil_f32(ctx, (const float*)p32, c->cells32, geom_of(c), (float*)q32, (double*)part,
                             &np, nullptr, N));
   return launch_cast_f32_f64(ctx, (const float*)q32, q_dev, n3);
 }

@@ -162,6 +162,8 @@ void resolve_timers(kp_context* ctx);
 struct kp_coeff {
   kp_context* ctx = nullptr;
   int L = 0, n0 = 0, N = 0;
+  int incl = 0;      // voxels per edge of the centred sub-cell carrying the cell value (n0: whole cell)
+  double bg = 0.0;   // coefficient outside the sub-cells (used when incl < n0)
   int precision = KP_FP64;
   double* cells = nullptr;   // L^3 (the stencils read the coefficient from here)
   float* cells32 = nullptr;  // L^3 float copy (mixed only)
@@ -207,7 +209,7 @@ constexpr int kRedBlocks = 1024;
 constexpr int kMaxPartials = 65536;
 // Number of GEMM tile configurations (double and 16-bit kernels).
 constexpr int kTiles64 = 4;
-constexpr int kTiles16 = 16;
+constexpr int kTiles16 = 12;
 
 // Times every tile configuration for a batch of nsys systems on scratch T, U,
 // X, Z (NULL: the context workspace, nsys = 1) and stores the fastest in tiles[3].
@@ -217,6 +219,26 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
 
 // ---- launchers (each returns a kp_status) ----------------------------------
 int launch_assemble(kp_context* ctx, kp_coeff* c);
+
+// How the stencils read a realization's coefficient: L^3 cell values, n0
+// voxels per cell edge; a voxel whose local coordinates (v mod n0 on every
+// axis) lie in [lo, hi) takes its cell's value, any other voxel the
+// background bg (Section 3.1: the centred sub-cell of edge 2 alpha / L;
+// lo = 0, hi = n0 for whole cells).
+struct CellGeom {
+  int L = 0, n0 = 0, lo = 0, hi = 0;
+  double bg = 0.0;
+  bool sub() const { return lo > 0 || hi < n0; }
+};
+inline CellGeom geom_of(const kp_coeff* c) {
+  CellGeom g;
+  g.L = c->L;
+  g.n0 = c->n0;
+  g.lo = (c->n0 - c->incl) / 2;
+  g.hi = g.lo + c->incl;
+  g.bg = c->bg;
+  return g;
+}
 // Sets *bad (device int, zeroed by the caller) when a cell is not finite or <= 0.
 int launch_validate_cells(kp_context* ctx, const double* cells, size_t n, int* bad);
 
@@ -224,13 +246,13 @@ int launch_validate_cells(kp_context* ctx, const double* cells, size_t n, int* b
 // by its L^3 cells (n0 grid intervals per cell), block partials of <p,q> (or
 // ||out||^2).  s (nullable) gates the systems (gate: enum Gate); bt.ws strides
 // the cells of successive realizations.
-int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, int L, int n0,
+int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, const CellGeom& cg,
                        const double* f, double* out, double* partial, int* nparts, const Scalars* s,
                        int N, const Batch& bt = Batch(), int gate = GATE_ACTIVE);
-int launch_stencil_f32(kp_context* ctx, const float* p, const float* cells, int L, int n0, float* out,
+int launch_stencil_f32(kp_context* ctx, const float* p, const float* cells, const CellGeom& cg, float* out,
                        double* partial, int* nparts, const Scalars* s, int N,
                        const Batch& bt = Batch());
-int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* cells, int L, int n0,
+int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* cells, const CellGeom& cg,
                             const double* f, float* out, double* partial, int* nparts,
                             const Scalars* s, int N, const Batch& bt = Batch(), int gate = GATE_ACTIVE);
 

@@ -58,7 +58,7 @@ int true_residual(Solver& S, bool into_r) {
     // double residual into the double scratch, then (optionally) into the float r.
     void* r64;
     KP_TRY(ws_get(S.ctx, WS_TMP64B, S.n3 * sizeof(double), &r64));
-    KP_TRY(launch_stencil_f64(S.ctx, S.x, S.c->cells, S.c->L, S.c->n0, S.fp, (double*)r64, S.part, &S.np, nullptr, S.N));
+    KP_TRY(launch_stencil_f64(S.ctx, S.x, S.c->cells, geom_of(S.c), S.fp, (double*)r64, S.part, &S.np, nullptr, S.N));
     KP_TRY(fin(S, 1, FIN_RR_NOCOUNT));
     if (into_r) {
       KP_TRY(launch_cast_f64_f32(S.ctx, (const double*)r64, (float*)S.r, S.n3));
@@ -67,11 +67,11 @@ int true_residual(Solver& S, bool into_r) {
     return KP_OK;
   }
   if (into_r) {
-    KP_TRY(launch_stencil_f64(S.ctx, S.x, S.c->cells, S.c->L, S.c->n0, S.fp, (double*)S.r, S.part, &S.np, nullptr, S.N));
+    KP_TRY(launch_stencil_f64(S.ctx, S.x, S.c->cells, geom_of(S.c), S.fp, (double*)S.r, S.part, &S.np, nullptr, S.N));
   } else {
     void* r64;
     KP_TRY(ws_get(S.ctx, WS_TMP64B, S.n3 * sizeof(double), &r64));
-    KP_TRY(launch_stencil_f64(S.ctx, S.x, S.c->cells, S.c->L, S.c->n0, S.fp, (double*)r64, S.part, &S.np, nullptr, S.N));
+    KP_TRY(launch_stencil_f64(S.ctx, S.x, S.c->cells, geom_of(S.c), S.fp, (double*)r64, S.part, &S.np, nullptr, S.N));
   }
   return fin(S, 1, FIN_RR_NOCOUNT);
 }
@@ -99,7 +99,7 @@ int precondition_and_update(Solver& S, int fin_mode, bool have_q) {
 
 int iteration(Solver& S, bool replace) {
   if (S.mixed) {
-    KP_TRY(launch_stencil_f32(S.ctx, (const float*)S.p, S.c->cells32, S.c->L, S.c->n0, (float*)S.q, S.part, &S.np, S.s, S.N));
+    KP_TRY(launch_stencil_f32(S.ctx, (const float*)S.p, S.c->cells32, geom_of(S.c), (float*)S.q, S.part, &S.np, S.s, S.N));
     KP_TRY(fin(S, 1, FIN_ALPHA));
     KP_TRY(launch_update_xr<float>(S.ctx, S.x, S.x32, (const float*)S.p, (float*)S.r, (const float*)S.q,
                                    S.x16, S.fp16, S.s, S.part, &S.np, S.n3));
@@ -108,13 +108,13 @@ int iteration(Solver& S, bool replace) {
       void* r64;
       KP_TRY(ws_get(S.ctx, WS_TMP64B, S.n3 * sizeof(double), &r64));
       KP_TRY(launch_fold(S.ctx, S.x, S.x32, S.n3, S.s));
-      KP_TRY(launch_resid_f64_to_f32(S.ctx, S.x, S.c->cells, S.c->L, S.c->n0, S.fp, (float*)S.r, S.part, &S.np, S.s, S.N));
+      KP_TRY(launch_resid_f64_to_f32(S.ctx, S.x, S.c->cells, geom_of(S.c), S.fp, (float*)S.r, S.part, &S.np, S.s, S.N));
       KP_TRY(fin(S, 1, FIN_RR_NOCOUNT));
       KP_TRY(launch_cast32_to16(S.ctx, (const float*)S.r, S.x16, S.n3, S.fp16, S.s));
     }
     return precondition_and_update(S, replace ? FIN_PREC_FR : FIN_PREC, true);
   }
-  KP_TRY(launch_stencil_f64(S.ctx, (const double*)S.p, S.c->cells, S.c->L, S.c->n0, nullptr, (double*)S.q, S.part, &S.np, S.s, S.N));
+  KP_TRY(launch_stencil_f64(S.ctx, (const double*)S.p, S.c->cells, geom_of(S.c), nullptr, (double*)S.q, S.part, &S.np, S.s, S.N));
   KP_TRY(fin(S, 1, FIN_ALPHA));
   KP_TRY(launch_update_xr<double>(S.ctx, S.x, nullptr, (const double*)S.p, (double*)S.r, (const double*)S.q,
                                   nullptr, 0, S.s, S.part, &S.np, S.n3));

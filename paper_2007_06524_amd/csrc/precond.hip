@@ -622,13 +622,15 @@ __global__ __launch_bounds__(256) void k_gemm_16c(GemmArgs g) {
 // keeps six of the eight fragments and reads two new ones (hi and lo planes).
 // The MFMA result of a lane is four consecutive data columns of one circulant
 // row; the data fragments' rows are assigned to columns so that each lane ends
-// with eight consecutive columns and writes them as one (16-bit) or two
-// (float) 16-byte stores.  Block: WAVES_M x (4 / WAVES_M) waves.  Stage (iii)
+// with 4 TND consecutive columns: float results go straight to memory as
+// 16-byte stores, 16-bit ones through a block staging tile in LDS so that the
+// stores cover whole rows of the block tile.  Block: WAVES_M x (4 / WAVES_M) waves.  Stage (iii)
 // runs over R circulants along K: two LDS buffers, the next circulant loaded
 // while the current one is used, one barrier per circulant.
 // Requires: N a multiple of 256, every tile interior (checked by wave_ok).
 template <int STAGE, int TMC, int TND, int WAVES_M, bool F16, typename TO>
 __global__ __launch_bounds__(256, 2) void k_gemm_16w(GemmArgs g) {
+  // (TMC = 4 with TND = 2 or 4 measured slower than 8 x 2 on every stage.)
   static_assert((TMC == 4 || TMC == 8) && TND % 2 == 0, "wave tile");
   constexpr int WM = 16 * TMC, WN = 16 * TND;
   constexpr int WAVES_N = 4 / WAVES_M;
@@ -638,6 +640,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_16w(GemmArgs g) {
   if (g.done && g.done[(long long)bo * g.done_stride]) return;
   extern __shared__ __attribute__((aligned(16))) bf16_t cpy[];  // [buffer][2][8][N + 8]
   __shared__ double red[20];
+  // Output staging tile of 16-bit results, rows padded by 16 bytes.
+  constexpr int SLD = BN + 8;
+  __shared__ __attribute__((aligned(16))) bf16_t stg[sizeof(TO) == 2 ? BM * SLD : 8];
   const bf16_t* __restrict__ B = (const bf16_t*)g.B + (long long)bz * g.sBb;
   TO* __restrict__ C = (TO*)g.C + (long long)bo * g.sCb;
   int mt, nt;
@@ -767,16 +772,32 @@ __global__ __launch_bounds__(256, 2) void k_gemm_16w(GemmArgs g) {
         }
       }
     } else {
+      // 16-bit results go through the block's staging tile (below): a wave holds
+      // only 32 or 64 bytes of each row, the block a whole run of BN columns.
+      const int r = wm * WM + 16 * c + l16;
 #pragma unroll
-      for (int h = 0; h < TND / 2; ++h) {  // eight columns per 16-byte store
+      for (int h = 0; h < TND / 2; ++h) {  // eight columns per 16-byte vector
         u32x4 w;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           w[e] = (uint32_t)cvt_out<TO, F16>(acc[c][2 * h + (e >> 1)][2 * (e & 1)] * oscale) |
                  ((uint32_t)cvt_out<TO, F16>(acc[c][2 * h + (e >> 1)][2 * (e & 1) + 1] * oscale) << 16);
-        *(u32x4*)(C + idx + 8 * h) = w;
+        *(u32x4*)(stg + r * SLD + wn * WN + 4 * TND * kg + 8 * h) = w;
       }
     }
+  }
+  if constexpr (!DOTS) {
+    // Whole rows of the block tile: BN / 8 vectors per row, each a 16-byte
+    // store; four or more consecutive lanes cover one row segment of BN
+    // columns (whole cache lines).
+    __syncthreads();
+    constexpr int VPR = BN / 8, ROWS = 256 / VPR;
+    const int vr = tid / VPR, vc = (tid - (tid / VPR) * VPR) * 8;
+    const long long col_b = (long long)(n0 / g.om.nd) * g.om.sn1 + (n0 - (n0 / g.om.nd) * g.om.nd) +
+                            (long long)bi * g.om.sb + vc;
+#pragma unroll
+    for (int r = vr; r < BM; r += ROWS)
+      *(u32x4*)(C + (long long)(m0 + r) * g.om.sm + col_b) = *(const u32x4*)(stg + r * SLD + vc);
   }
   if constexpr (DOTS) {
     if (dots) {
@@ -809,9 +830,7 @@ constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}}
 constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 0},  {128, 64, 64, 0},   {64, 128, 64, 0},
                                      {128, 128, 64, 0}, {128, 128, 32, 0},  {64, 128, 32, 0},
                                      {64, 128, 64, 1},  {128, 128, 64, 1},  {128, 128, 32, 1},
-                                     {32, 64, 32, 1},   {128, 128, 8, 2},   {256, 64, 8, 2},
-                                     {64, 256, 4, 2},   {128, 128, 4, 2},   {256, 64, 4, 2},
-                                     {128, 64, 4, 2}};
+                                     {32, 64, 32, 1},   {128, 128, 8, 2},   {256, 64, 8, 2}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
@@ -889,10 +908,11 @@ bool circ_ok(const GemmArgs& g, int BM, int BN, int BK) {
 }
 // Can k_gemm_16w run it with block tile BM x BN?  As circ_ok, plus N a
 // multiple of 256 (eight K steps per ring turn inside one circulant), K whole
-// circulants, and 16-byte aligned runs of eight columns in the output (and in
-// r, q for the fused dot products).
+// circulants, every block's BN columns inside one contiguous output run, and
+// 16-byte aligned runs of eight columns in the output (and in r, q for the
+// fused dot products).
 bool wave_ok(const GemmArgs& g, int BM, int BN) {
-  const bool out = g.om.sn2 == 1 && (g.om.nd == INT_MAX || g.om.nd % 64 == 0) && g.om.sm % 8 == 0 && g.om.sn1 % 8 == 0 &&
+  const bool out = g.om.sn2 == 1 && (g.om.nd == INT_MAX || g.om.nd % BN == 0) && g.om.sm % 8 == 0 && g.om.sn1 % 8 == 0 &&
                    g.om.sb % 8 == 0 && g.sCb % 8 == 0 && aligned16(g.C);
   const bool dots = !g.dpart || (aligned16(g.dr) && (!g.dq || aligned16(g.dq)));
   return g.circ && g.a_lo && vec_ok(g) && g.cn % 256 == 0 && g.M % BM == 0 && g.Nn % BN == 0 &&
@@ -941,11 +961,7 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
     case 8: launch16<STAGE, 128, 128, 32, 1, TO>(ctx, g, batch, f16); break;
     case 9: launch16<STAGE, 32, 64, 32, 1, TO>(ctx, g, batch, f16); break;
     case 10: launch16<STAGE, 128, 128, 8, 2, TO>(ctx, g, batch, f16); break;
-    case 11: launch16<STAGE, 256, 64, 8, 2, TO>(ctx, g, batch, f16); break;
-    case 12: launch16<STAGE, 64, 256, 4, 2, TO>(ctx, g, batch, f16); break;
-    case 13: launch16<STAGE, 128, 128, 4, 2, TO>(ctx, g, batch, f16); break;
-    case 14: launch16<STAGE, 256, 64, 4, 2, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 128, 64, 4, 2, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 256, 64, 8, 2, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;

@@ -36,9 +36,11 @@ __device__ __forceinline__ void block_sum_store(double v, double* out) {
 }
 
 // One thread per node; the eight voxels around node p are v = p - 1 + d, d in {0,1}^3.
+// A voxel takes its cell's value when its local coordinates v mod n0 all lie in
+// [lo, hi) (the centred sub-cell; lo = 0, hi = n0 for whole cells), else bg.
 __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ cells, int L, int n0,
-                                                  int N, double h, double* __restrict__ w64,
-                                                  double* __restrict__ f) {
+                                                  int lo, int hi, double bg, int N, double h,
+                                                  double* __restrict__ w64, double* __restrict__ f) {
   const size_t n3 = (size_t)N * N * N;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n3) return;
@@ -46,14 +48,22 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ cel
   const int p2 = (int)((idx / N) % N);
   const int p1 = (int)(idx / ((size_t)N * N));
   int c1[2], c2[2], c3[2];
-  c1[0] = ((p1 + N - 1) % N) / n0; c1[1] = p1 / n0;
-  c2[0] = ((p2 + N - 1) % N) / n0; c2[1] = p2 / n0;
-  c3[0] = ((p3 + N - 1) % N) / n0; c3[1] = p3 / n0;
+  bool in1[2], in2[2], in3[2];
+  const int v1[2] = {(p1 + N - 1) % N, p1}, v2[2] = {(p2 + N - 1) % N, p2}, v3[2] = {(p3 + N - 1) % N, p3};
+  for (int d = 0; d < 2; ++d) {
+    c1[d] = v1[d] / n0;
+    c2[d] = v2[d] / n0;
+    c3[d] = v3[d] / n0;
+    const int l1 = v1[d] - c1[d] * n0, l2 = v2[d] - c2[d] * n0, l3 = v3[d] - c3[d] * n0;
+    in1[d] = l1 >= lo && l1 < hi;
+    in2[d] = l2 >= lo && l2 < hi;
+    in3[d] = l3 >= lo && l3 < hi;
+  }
   double a[2][2][2];
   for (int d1 = 0; d1 < 2; ++d1)
     for (int d2 = 0; d2 < 2; ++d2)
       for (int d3 = 0; d3 < 2; ++d3)
-        a[d1][d2][d3] = cells[((size_t)c1[d1] * L + c2[d2]) * L + c3[d3]];
+        a[d1][d2][d3] = (in1[d1] && in2[d2] && in3[d3]) ? cells[((size_t)c1[d1] * L + c2[d2]) * L + c3[d3]] : bg;
   // Edge (p, p+e_l): voxel layer p_l along l, p_t - 1 or p_t across.
   const double w0 = (((a[1][1][1] + a[1][0][1]) + a[1][1][0]) + a[1][0][0]) / 4.0;
   const double w0m = (((a[0][1][1] + a[0][0][1]) + a[0][1][0]) + a[0][0][0]) / 4.0;
@@ -73,11 +83,13 @@ constexpr int kTX = 64;  // i3 extent of a tile (one wavefront)
 constexpr int kTY = 4;   // i2 extent of a tile (four wavefronts)
 
 // Coefficient of one realization as the stencil reads it: the L^3 cell values
-// [c1][c2][c3] (cell of voxel v: v / n0 per axis).
+// [c1][c2][c3] (cell of voxel v: v / n0 per axis) and, for sub-cell
+// inclusions, the voxel range [lo, hi) of the sub-cell and the background.
 template <typename TC>
 struct Cells {
   const TC* a;
-  int L, n0;
+  int L, n0, lo, hi;
+  TC bg;
 };
 
 // 2.5D tiled stencil on the cell values.  The edge weights are not read from
@@ -98,8 +110,11 @@ struct Cells {
 // and dot = <u, K u>.  MODE 1: out = f - K u and dot = ||f - K u||^2 (true
 // residual).  Cell type TC, accumulation type C, output type TO.
 // blockIdx.z = system * gz + plane chunk (Batch layout; bt.ws strides the
-// cells of successive realizations).
-template <typename TU, typename TC, typename TO, typename C, int MODE>
+// cells of successive realizations).  INCL: sub-cell inclusions; the voxel
+// values are the cell values where the voxel's plane, row and column all lie
+// inside the sub-cell range and the background elsewhere (three per-thread
+// masks and one per plane), again summed in the assembly kernel's order.
+template <typename TU, typename TC, typename TO, typename C, int MODE, bool INCL>
 __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u, Cells<TC> cc,
                                                  const double* __restrict__ f,
                                                  TO* __restrict__ out,
@@ -127,12 +142,18 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u, Cells
   const int i3m = (i3 == 0) ? N - 1 : i3 - 1;
   const int i3p = (i3 + 1 >= N) ? 0 : i3 + 1;
   const size_t col = (size_t)i2 * N + i3;
-  // Transverse cell offsets: [d2][d3] -> c2 * L + c3 for d = 0 (p - 1) and 1 (p).
+  // Transverse cell offsets: [d2][d3] -> c2 * L + c3 for d = 0 (p - 1) and 1 (p);
+  // with inclusions, whether voxel column [d2][d3] lies in the sub-cell's range.
   int toff[2][2] = {{0, 0}, {0, 0}};
+  bool tin[2][2] = {{true, true}, {true, true}};
   if (act) {
     const int c2[2] = {i2m / n0, i2 / n0}, c3[2] = {i3m / n0, i3 / n0};
+    const int l2[2] = {i2m - c2[0] * n0, i2 - c2[1] * n0}, l3[2] = {i3m - c3[0] * n0, i3 - c3[1] * n0};
     for (int d2 = 0; d2 < 2; ++d2)
-      for (int d3 = 0; d3 < 2; ++d3) toff[d2][d3] = c2[d2] * L + c3[d3];
+      for (int d3 = 0; d3 < 2; ++d3) {
+        toff[d2][d3] = c2[d2] * L + c3[d3];
+        tin[d2][d3] = l2[d2] >= cc.lo && l2[d2] < cc.hi && l3[d3] >= cc.lo && l3[d3] < cc.hi;
+      }
   }
   auto layer = [&](int c1, C (&a)[2][2]) {
     const size_t base = (size_t)c1 * L * L;
@@ -166,12 +187,33 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u, Cells
       const C u3m = (tx > 0) ? (C)su[ty][tx - 1] : (C)u[base + (size_t)i2 * N + i3m];
       const C u3p = (tx + 1 < kTX && i3 + 1 < N) ? (C)su[ty][tx + 1] : (C)u[base + (size_t)i2 * N + i3p];
       const C q = (C)0.25;
-      const C w0c = (((a1[1][1] + a1[0][1]) + a1[1][0]) + a1[0][0]) * q;
-      const C w0m = (((a0[1][1] + a0[0][1]) + a0[1][0]) + a0[0][0]) * q;
-      const C w1c = (((a1[1][1] + a0[1][1]) + a1[1][0]) + a0[1][0]) * q;
-      const C w1m = (((a1[0][1] + a0[0][1]) + a1[0][0]) + a0[0][0]) * q;
-      const C w2c = (((a1[1][1] + a0[1][1]) + a1[0][1]) + a0[0][1]) * q;
-      const C w2m = (((a1[1][0] + a0[1][0]) + a1[0][0]) + a0[0][0]) * q;
+      C e0[2][2], e1[2][2];  // voxel values of layers z - 1 and z
+      if constexpr (INCL) {
+        const int r0 = rz == 0 ? n0 - 1 : rz - 1;
+        const bool in0 = r0 >= cc.lo && r0 < cc.hi, in1 = rz >= cc.lo && rz < cc.hi;
+        const C bg = (C)cc.bg;
+#pragma unroll
+        for (int d2 = 0; d2 < 2; ++d2)
+#pragma unroll
+          for (int d3 = 0; d3 < 2; ++d3) {
+            e0[d2][d3] = (in0 && tin[d2][d3]) ? a0[d2][d3] : bg;
+            e1[d2][d3] = (in1 && tin[d2][d3]) ? a1[d2][d3] : bg;
+          }
+      } else {
+#pragma unroll
+        for (int d2 = 0; d2 < 2; ++d2)
+#pragma unroll
+          for (int d3 = 0; d3 < 2; ++d3) {
+            e0[d2][d3] = a0[d2][d3];
+            e1[d2][d3] = a1[d2][d3];
+          }
+      }
+      const C w0c = (((e1[1][1] + e1[0][1]) + e1[1][0]) + e1[0][0]) * q;
+      const C w0m = (((e0[1][1] + e0[0][1]) + e0[1][0]) + e0[0][0]) * q;
+      const C w1c = (((e1[1][1] + e0[1][1]) + e1[1][0]) + e0[1][0]) * q;
+      const C w1m = (((e1[0][1] + e0[0][1]) + e1[0][0]) + e0[0][0]) * q;
+      const C w2c = (((e1[1][1] + e0[1][1]) + e1[0][1]) + e0[0][1]) * q;
+      const C w2m = (((e1[1][0] + e0[1][0]) + e1[0][0]) + e0[0][0]) * q;
       C ku = w0c * (uc - un) + w0m * (uc - um);
       ku += w1c * (uc - u2p) + w1m * (uc - u2m);
       ku += w2c * (uc - u3p) + w2m * (uc - u3m);
@@ -219,8 +261,13 @@ int run_stencil(kp_context* ctx, const TU* u, Cells<TC> cc, const double* f, TO*
     TZ *= 2;
     gz = (N + TZ - 1) / TZ;
   }
-  hipLaunchKernelGGL((k_stencil<TU, TC, TO, C, MODE>), dim3(gx, gy, gz * bt.nsys), dim3(256), 0,
-                     ctx->stream, u, cc, f, out, partial, s, gate, N, TZ, gz, bt);
+  const dim3 grid(gx, gy, gz * bt.nsys);
+  if (cc.lo > 0 || cc.hi < cc.n0)
+    hipLaunchKernelGGL((k_stencil<TU, TC, TO, C, MODE, true>), grid, dim3(256), 0, ctx->stream, u, cc, f,
+                       out, partial, s, gate, N, TZ, gz, bt);
+  else
+    hipLaunchKernelGGL((k_stencil<TU, TC, TO, C, MODE, false>), grid, dim3(256), 0, ctx->stream, u, cc,
+                       f, out, partial, s, gate, N, TZ, gz, bt);
   KP_HIP(hipGetLastError());
   *nparts = gx * gy * gz;
   return KP_OK;
@@ -250,8 +297,9 @@ int launch_assemble(kp_context* ctx, kp_coeff* c) {
   ScopedTimer tm(ctx, KP_TIMER_ASSEMBLE);
   const size_t n3 = (size_t)c->N * c->N * c->N;
   const int blocks = (int)((n3 + 255) / 256);
-  hipLaunchKernelGGL(k_assemble, dim3(blocks), dim3(256), 0, ctx->stream, c->cells, c->L, c->n0,
-                     c->N, 1.0 / c->N, c->w64, c->f);
+  const CellGeom cg = geom_of(c);
+  hipLaunchKernelGGL(k_assemble, dim3(blocks), dim3(256), 0, ctx->stream, c->cells, c->L, c->n0, cg.lo,
+                     cg.hi, cg.bg, c->N, 1.0 / c->N, c->w64, c->f);
   KP_HIP(hipGetLastError());
   if (c->cells32) return launch_cast_f64_f32(ctx, c->cells, c->cells32, (size_t)c->L * c->L * c->L);
   return KP_OK;
@@ -262,10 +310,15 @@ int stencil_parts_max(int N) {
   return ((N + kTX - 1) / kTX) * ((N + kTY - 1) / kTY) * ((N + 3) / 4);
 }
 
-int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, int L, int n0,
+template <typename TC>
+Cells<TC> cells_of(const TC* a, const CellGeom& cg) {
+  return Cells<TC>{a, cg.L, cg.n0, cg.lo, cg.hi, (TC)cg.bg};
+}
+
+int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, const CellGeom& cg,
                        const double* f, double* out, double* partial, int* nparts, const Scalars* s,
                        int N, const Batch& bt, int gate) {
-  const Cells<double> cc{cells, L, n0};
+  const Cells<double> cc = cells_of(cells, cg);
   if (f)
     return run_stencil<double, double, double, double, 1>(ctx, p, cc, f, out, partial, nparts, s, gate,
                                                           N, bt);
@@ -273,17 +326,17 @@ int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, in
                                                         gate, N, bt);
 }
 
-int launch_stencil_f32(kp_context* ctx, const float* p, const float* cells, int L, int n0, float* out,
+int launch_stencil_f32(kp_context* ctx, const float* p, const float* cells, const CellGeom& cg, float* out,
                        double* partial, int* nparts, const Scalars* s, int N, const Batch& bt) {
-  return run_stencil<float, float, float, float, 0>(ctx, p, Cells<float>{cells, L, n0}, nullptr, out,
-                                                    partial, nparts, s, GATE_ACTIVE, N, bt);
+  return run_stencil<float, float, float, float, 0>(ctx, p, cells_of(cells, cg), nullptr, out, partial,
+                                                    nparts, s, GATE_ACTIVE, N, bt);
 }
 
-int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* cells, int L, int n0,
+int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* cells, const CellGeom& cg,
                             const double* f, float* out, double* partial, int* nparts,
                             const Scalars* s, int N, const Batch& bt, int gate) {
-  return run_stencil<double, double, float, double, 1>(ctx, x, Cells<double>{cells, L, n0}, f, out,
-                                                       partial, nparts, s, gate, N, bt);
+  return run_stencil<double, double, float, double, 1>(ctx, x, cells_of(cells, cg), f, out, partial,
+                                                       nparts, s, gate, N, bt);
 }
 
 }  // namespace kp
