@@ -288,9 +288,9 @@ int pcg_solve(kp_context* ctx, const kp_coeff* coeff, const kp_precond* pc, int 
  * (j = 0..2) solves corrector j+1 of instance i into x_dev[3 i + j] (device,
  * N_i^3 doubles, caller-owned; read as the initial guess when opts->use_x0,
  * always overwritten with the zero-mean solution).
- * Instances that share a preconditioner and the cell size n0 form a group;
- * every PCG step of a
- * group runs as one launch over all its systems, the groups run as
+ * Instances that share a preconditioner and the coefficient geometry (n0,
+ * sub-cell size, background) form a group; every PCG step of a group runs as
+ * one launch over all its systems, the groups run as
  * concurrent branches of one HIP graph that holds opts->check_every
  * iterations (0: 16), and the graph is replayed until every system has
  * stopped.  Convergence is decided per system on the device, by the true
@@ -307,6 +307,47 @@ int pcg_solve(kp_context* ctx, const kp_coeff* coeff, const kp_precond* pc, int 
 int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* const* coeffs,
                       const kp_precond* const* preconds, double* const* x_dev,
                       const kp_solve_opts* opts, kp_solve_stats* stats, double* ahom);
+
+/* ---- Monte-Carlo statistics (Section 5.3) ------------------------------- */
+
+typedef struct {
+  int realizations;        /* M                                                 */
+  int batch;               /* realizations per batched solve (B)                */
+  int chunks;              /* batched solves run (ceil(M / B))                  */
+  int status;              /* worst kp_status over the systems                  */
+  long long iters;         /* PCG iterations summed over the 3 M systems        */
+  double max_relres_true;  /* largest true relative residual at exit            */
+  double ms;               /* wall time of the whole call                       */
+} kp_mc_stats;
+
+/* Empirical homogenized matrix of M realizations at one RVE size L: for each
+ * realization the three corrector solves and a_hom (eq. Ahom3_m_entry_comp),
+ * then entry by entry the empirical average (eq. A_hom_Empir)
+ *   mean = (1/M) sum_m A^(m)
+ * and the empirical standard deviation sigma_L^M (normalization M - 1)
+ *   sd = sqrt( sum_m (A^(m) - mean)^2 / (M - 1) ),
+ * both summed on the device in the order m = 0..M-1.
+ *   a_cells: host, M * L^3 doubles, realization m at m L^3, [c1][c2][c3],
+ *            finite and > 0 (the caller draws them: the random numbers of the
+ *            method are an input).
+ *   incl, background: the coefficient geometry of setup_coeff_inclusions
+ *            (incl = n0: whole cells).
+ *   pc: preconditioner of N = n0 L in the precision to solve in (also the
+ *            precision of the coefficient objects built here).
+ *   opts: as pcg_solve_batched (NULL: defaults).
+ *   batch: realizations per batched solve; <= 0 sizes it to about 32 GiB of
+ *            solver state.  The realizations stream through B reused
+ *            coefficient objects (kp_coeff_update between chunks).
+ *   ahom: host, 9 M doubles (may be NULL): every realization's matrix.
+ *   mean, sd: host, 9 doubles each, row-major.
+ *   stats: host (may be NULL).
+ * Returns KP_OK, KP_NOT_CONVERGED or KP_ERR_BREAKDOWN as pcg_solve_batched
+ * (worst over the chunks; the statistics are still formed), or an error:
+ * KP_ERR_ARG for M < 2, n0 L != pc's N, bad cells or geometry.  Synchronizes
+ * the stream. */
+int kp_mc_homogenize(kp_context* ctx, int L, int n0, int incl, double background, int M,
+                     const double* a_cells, const kp_precond* pc, const kp_solve_opts* opts,
+                     int batch, double* ahom, double* mean, double* sd, kp_mc_stats* stats);
 
 /* Homogenized matrix of one realization (eq. Ahom3_m_entry_comp):
  *   ahom[i][j] = delta_ij mean(a) - h sum_p phi_i(p) f_j(p),  i,j = 1..3,

@@ -24,7 +24,7 @@ from ._lib import (KP_FP64, KP_MIXED_BF16, KP_MIXED_FP16, KP_NOT_CONVERGED, KP_O
                    check, load)
 
 __all__ = ["Context", "Coeff", "Precond", "solve", "solve_batched", "homogenized_matrix", "stiffness_apply",
-           "lowrank_factors", "KronPCGError", "PRECISIONS", "KP_FP64", "KP_MIXED_BF16",
+           "lowrank_factors", "mc_homogenize", "KronPCGError", "PRECISIONS", "KP_FP64", "KP_MIXED_BF16",
            "KP_MIXED_FP16", "KP_OK", "KP_NOT_CONVERGED", "KP_WARN_RHS_MEAN"]
 
 _live_contexts = weakref.WeakSet()
@@ -279,6 +279,34 @@ def solve_batched(ctx: Context, coeffs, preconds, xs=None, tol: float = 1e-8, ma
     check(st, allow=(KP_OK, KP_NOT_CONVERGED))
     A = np.frombuffer(ah, dtype=np.float64).reshape(n, 3, 3).copy() if want_ahom else None
     return xs, [s.as_dict() for s in stats], A, st
+
+
+def mc_homogenize(ctx: Context, cells, n0: int, pc: Precond, inclusion: int | None = None,
+                  background: float | None = None, tol: float = 1e-8, maxit: int = 2000,
+                  replace_every: int | None = None, check_every: int = 0, batch: int = 0):
+    """kp_mc_homogenize: a_hom of M realizations (cells: (M, L, L, L) float64) and the
+    empirical mean and standard deviation (M - 1 normalization) of every entry.
+
+    Returns (ahoms (M, 3, 3), mean (3, 3), std (3, 3), stats dict, status)."""
+    cells = np.ascontiguousarray(cells, dtype=np.float64)
+    if cells.ndim != 4 or len(set(cells.shape[1:])) != 1:
+        raise ValueError("cells must be an (M, L, L, L) array")
+    M, L = cells.shape[0], cells.shape[1]
+    incl = int(n0) if inclusion is None else int(inclusion)
+    bg = 0.0 if background is None else float(background)
+    if replace_every is None:
+        replace_every = 0 if pc.precision == KP_FP64 else 25
+    opts = SolveOpts(float(tol), int(maxit), int(replace_every), 0, int(check_every))
+    ah = np.zeros((M, 3, 3))
+    mean = np.zeros((3, 3))
+    sd = np.zeros((3, 3))
+    st = _lib.MCStats()
+    dp = C.POINTER(C.c_double)
+    status = load().kp_mc_homogenize(ctx.handle, L, int(n0), incl, bg, M, cells.ctypes.data_as(dp),
+                                     pc.handle, C.byref(opts), int(batch), ah.ctypes.data_as(dp),
+                                     mean.ctypes.data_as(dp), sd.ctypes.data_as(dp), C.byref(st))
+    check(status, allow=(KP_OK, KP_NOT_CONVERGED))
+    return ah, mean, sd, st.as_dict(), status
 
 
 def homogenized_matrix(ctx: Context, coeff: Coeff, phis) -> np.ndarray:

@@ -52,6 +52,14 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class MCStats(C.Structure):
+    _fields_ = [("realizations", C.c_int), ("batch", C.c_int), ("chunks", C.c_int), ("status", C.c_int),
+                ("iters", C.c_longlong), ("max_relres_true", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class TileTiming(C.Structure):
     _fields_ = [("stage", C.c_int), ("bm", C.c_int), ("bn", C.c_int), ("bk", C.c_int), ("order", C.c_int),
                 ("circ", C.c_int), ("ms", C.c_double)]
@@ -94,6 +102,10 @@ SIGNATURES = {
     "kp_free_precond": (C.c_int, [C.c_void_p]),
     "pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                             C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+    "kp_mc_homogenize": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
+                                   C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_int,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.c_void_p]),
     "pcg_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                     C.POINTER(C.c_void_p), C.POINTER(SolveOpts), C.POINTER(SolveStats),
                                     C.POINTER(C.c_double)]),

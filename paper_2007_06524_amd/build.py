@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkronpcg.so")
-SOURCES = ["context.hip", "stencil.hip", "blas1.hip", "precond.hip", "pcg.hip", "batch.hip", "lowrank.cpp"]
+SOURCES = ["context.hip", "stencil.hip", "blas1.hip", "precond.hip", "pcg.hip", "batch.hip",
+           "montecarlo.hip", "lowrank.cpp"]
 ARCH = "gfx950"
 
 

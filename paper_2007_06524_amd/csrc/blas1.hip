@@ -66,6 +66,13 @@ __device__ double x16_scale_for(double rr, double n3) {
   return sc;
 }
 
+// Reliable updates in mixed precision: once the recursive ||r|| has fallen by
+// 1e4 below the last true residual, the float recursion is near the end of
+// its accuracy (float unit roundoff 6e-8 times the larger residual it carries
+// errors from), so the residual is replaced by f - K x in double.  With the
+// fixed replacement period this only fires for fast convergence.
+constexpr double kReliableDrop = 1e-8;  // on ||r||^2
+
 __device__ void stop(Scalars* s, int status) {
   s->done = 1;
   s->status = status;
@@ -124,12 +131,17 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
       if (mode == FIN_RR) s->iters += 1;
       const double sc = x16_scale_for(rr, n3);
       s->x16_scale_next = sc;
-      if (mode == FIN_RR_NOCOUNT) s->x16_scale = sc;  // followed by a fresh conversion
+      if (mode == FIN_RR_NOCOUNT) {
+        s->x16_scale = sc;  // followed by a fresh conversion
+        s->rr_ref = rr;     // a true residual
+      }
       if (!finite(rr)) {
         stop(s, 3);
       } else if (rr <= s->tol2ff) {
         s->done = 1;
         if (mode == FIN_RR_NOCOUNT) s->status = 1;  // a true residual: converged
+      } else if (mode == FIN_RR && s->flexible && rr <= kReliableDrop * s->rr_ref) {
+        s->done = 1;  // the single solver's host loop takes the true residual and restarts
       }
       break;
     }
@@ -143,7 +155,8 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
         break;
       }
       s->check = rr <= s->tol2ff || s->iters >= s->maxit ||
-                 (s->replace_every > 0 && s->iters % s->replace_every == 0);
+                 (s->replace_every > 0 && s->iters % s->replace_every == 0) ||
+                 (s->flexible && rr <= kReliableDrop * s->rr_ref);
       if (s->check) s->rr_rec = rr;
       break;
     }
@@ -156,6 +169,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
         break;
       }
       s->rr = rr;
+      s->rr_ref = rr;
       if (rr <= s->tol2ff) {
         stop(s, 1);
       } else if (s->iters >= s->maxit) {

@@ -44,6 +44,7 @@ struct Scalars {
   double x16_scale_next;  // the scale for the next conversion (from the newest ||r||)
   double sums[8]; // scratch results of the last multi-value reduction
   double rr_rec;  // recursive ||r||^2 when the last true residual was taken
+  double rr_ref;  // ||f - K x||^2 at the last true residual (reliable-update reference)
   int done;       // 1: converged (recursive test) or broken down; kernels then no-op
   int breakdown;  // 1: <p,Kp> <= 0, rho <= 0 or non-finite
   int iters;      // iterations completed

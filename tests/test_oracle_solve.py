@@ -224,3 +224,23 @@ def test_empirical_statistics():
     np.testing.assert_allclose(s4, np.abs(A[0] - A[1]) / np.sqrt(2.0), rtol=1e-13)
     with pytest.raises(ValueError):
         empirical_statistics(A[:1])
+
+
+def test_statistics_decay_rate():
+    """eq. var: the standard deviation of a_hom over realizations decays like
+    L^(-d/2) in the RVE size.  Oracle on whole cells (n0 = 1), Bernoulli{1, 10},
+    M = 64 realizations at L = 4, 8, 16: the fitted log-log slope of sigma_L^M
+    of a_11 lies within 0.4 of -3/2, and the empirical average barely moves
+    (its change is within a few standard errors)."""
+    from oracle.homogenize import empirical_statistics
+    from workloads import mc_realizations
+    Ls, sig, means = (4, 8, 16), [], []
+    for L in Ls:
+        cells = mc_realizations(L, 64, 1.0, 10.0, 0.5, seed=7)
+        A = np.stack([solve_correctors(c, 1, tol=1e-10)["ahom"] for c in cells])
+        m, s = empirical_statistics(A)
+        sig.append(s[0, 0])
+        means.append(m[0, 0])
+    slope = np.polyfit(np.log(Ls), np.log(sig), 1)[0]
+    assert -1.9 <= slope <= -1.1, slope
+    assert abs(means[2] - means[1]) <= 4 * (sig[1] + sig[2]) / np.sqrt(64)

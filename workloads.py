@@ -31,6 +31,8 @@ __all__ = [
     "CONFIGS",
     "config_cells",
     "batched_realizations",
+    "mc_realizations",
+    "MC_FIGURE",
 ]
 
 
@@ -106,3 +108,21 @@ def batched_realizations(count: int = 96, sizes=(8, 12, 16, 24), sigma: float = 
     """Realizations with uneven L cycling over `sizes`, log-normal cells."""
     children = np.random.SeedSequence(seed).spawn(count)
     return [cells_lognormal(sizes[m % len(sizes)], sigma, children[m]) for m in range(count)]
+
+
+def mc_realizations(L: int, M: int, lo: float, hi: float, p: float, seed: int) -> np.ndarray:
+    """M i.i.d. two-valued realizations on the L^3 lattice, shape (M, L, L, L).
+
+    Realization m draws from its own child of SeedSequence((seed, L)), so the
+    first M realizations do not depend on how many more are drawn.
+    """
+    children = np.random.SeedSequence((seed, L)).spawn(M)
+    return np.stack([cells_bernoulli(L, lo, hi, p, children[m]) for m in range(M)])
+
+
+# The paper's Monte-Carlo experiment in 3D (Fig. Emp_a12_M20): n0 = 4,
+# alpha = 1/4 (sub-cells of 2 voxels per edge), binary {lambda = 0.4, 1} with
+# lambda as the background, L = 2^p, M realizations per L.  The probability of
+# a perturbed cell is not stated; 1/2 is used.
+MC_FIGURE = dict(n0=4, incl=2, background=0.4, lo=0.4, hi=1.0, p=0.5, sizes=(2, 4, 8, 16, 32, 64),
+                 M=100, seed=6)
