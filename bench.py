@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true", help="use the size heuristic for GEMM tiles")
+    ap.add_argument("--no-mc", action="store_true", help="skip the Monte-Carlo statistics section")
+    ap.add_argument("--mc-only", action="store_true", help="run only the Monte-Carlo statistics section")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched section (96 realizations of uneven L)")
     ap.add_argument("--batched-only", action="store_true",
@@ -199,6 +201,46 @@ def batched_section(kp, ctx, eps, reps=2, precisions=("mixed_bf16", "fp64")):
     return out
 
 
+def montecarlo_section(kp, ctx, eps, sizes=None, M=None, precision="mixed_bf16"):
+    """The paper's Monte-Carlo experiment in 3D (Fig. Emp_a12_M20): n0 = 4, sub-cells of
+    alpha = 1/4, binary {lambda = 0.4, 1}, M realizations at each L = 2^p; a_hom of every
+    realization, its empirical mean and standard deviation, and the fitted decay rate of
+    sigma_L(a_11) (eq. var predicts L^(-3/2)).  Timed per L, preconditioner build
+    excluded (built once per N, as the paper does)."""
+    import numpy as np
+    import torch
+
+    from workloads import MC_FIGURE, mc_realizations
+
+    cfg = MC_FIGURE
+    sizes = sizes or cfg["sizes"]
+    M = M or cfg["M"]
+    rows = []
+    for L in sizes:
+        cells = mc_realizations(L, M, cfg["lo"], cfg["hi"], cfg["p"], seed=cfg["seed"])
+        pc = kp.Precond(ctx, L * cfg["n0"], eps, 0, precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A, mean, sd, st, status = kp.mc_homogenize(ctx, cells, cfg["n0"], pc, inclusion=cfg["incl"],
+                                                   background=cfg["background"])
+        dt = time.perf_counter() - t0
+        rows.append({"L": L, "N": L * cfg["n0"], "M": M, "seconds": dt, "realizations_per_s": M / dt,
+                     "status": status, "batch": st["batch"], "iters_per_system": st["iters"] / (3.0 * M),
+                     "max_relres_true": st["max_relres_true"], "mean_a11": mean[0, 0], "sd_a11": sd[0, 0],
+                     "mean_offdiag_max": float(np.abs(mean - np.diag(np.diag(mean))).max()),
+                     "sd_diag": [sd[0, 0], sd[1, 1], sd[2, 2]]})
+        pc.free()
+    Ls = np.array([r["L"] for r in rows], dtype=float)
+    sig = np.array([r["sd_a11"] for r in rows])
+    big = Ls >= 4
+    slope = float(np.polyfit(np.log(Ls[big]), np.log(sig[big]), 1)[0]) if big.sum() >= 2 else None
+    return {"workload": f"Fig. Emp_a12_M20 setting: n0 = {cfg['n0']}, alpha = 1/4 (sub-cells of "
+                        f"{cfg['incl']} voxels), a in {{{cfg['lo']}, {cfg['hi']}}} with P({cfg['hi']}) = "
+                        f"{cfg['p']}, background {cfg['background']}, M = {M} per L, tol 1e-8, {precision}",
+            "per_L": rows, "sigma_decay_slope_L_ge_4": slope,
+            "total_s": float(sum(r["seconds"] for r in rows))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -211,6 +253,13 @@ def main():
     import paper_2007_06524_amd as kp
     from paper_2007_06524_amd.profiling import kernel_source_digest, measured_traffic
     from workloads import CONFIGS, config_cells
+
+    if args.mc_only:
+        ctx = kp.Context(0)
+        out = montecarlo_section(kp, ctx, args.eps)
+        ctx.close()
+        print(json.dumps(out))
+        return
 
     if args.batched_only:
         ctx = kp.Context(0)
@@ -350,6 +399,13 @@ def main():
         pc.free()
         co = pc = None
         result["batched"] = batched_section(kp, ctx, args.eps)
+
+    if not args.no_mc:
+        if co is not None:
+            co.free()
+            pc.free()
+            co = pc = None
+        result["montecarlo"] = montecarlo_section(kp, ctx, args.eps)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(cells, n0, args.cpu_iters)
