@@ -217,6 +217,17 @@ int kp_lowrank_factors(int N, double eps, int rank, double* factors_out, size_t 
 int build_preconditioner(kp_context* ctx, int N, double eps, int rank, int precision,
                          kp_precond** out, kp_precond_info* info);
 
+/* The paper's first approach (Section 4.2): the exact pseudo-inverse of the
+ * periodic Laplacian, diagonal in the Fourier basis (eq. 3a with the constant
+ * prefactor dropped), z = F^-1 (g F r) with g(k) = 1 / sum_l 4 sin^2(pi k_l / N)
+ * and g(0) = 0, applied by double-precision 3D real-to-complex FFTs (hipFFT)
+ * and one symbol-scaling kernel.  FP64 only, one system at a time: usable
+ * with pcg_solve (FP64 coefficient) and kp_precond_apply, rejected by
+ * pcg_solve_batched (KP_ERR_STATE); rank 0, nothing to autotune.  A
+ * comparison point for the low-rank preconditioner.  Errors: KP_ERR_ARG for
+ * N outside [2, 2048], KP_ERR_HIP when a plan cannot be made. */
+int build_preconditioner_fft(kp_context* ctx, int N, kp_precond** out);
+
 /* Same, from caller-supplied canonical factors: factors is host memory of
  * 3*R*N doubles [l][k][i], each u_l^(k) even (u(i) = u(N-i)), 1 <= R <= 16. */
 int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors,

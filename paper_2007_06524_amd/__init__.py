@@ -158,16 +158,22 @@ class Coeff:
 
 
 class Precond:
-    """Low-rank preconditioner (build_preconditioner / kp_precond_from_factors)."""
+    """Low-rank preconditioner (build_preconditioner / kp_precond_from_factors), or with
+    fft=True the exact FFT-diagonalized one (build_preconditioner_fft, FP64)."""
 
     def __init__(self, ctx: Context, N: int, eps: float = 1e-3, rank: int = 0, precision="fp64",
-                 factors: np.ndarray | None = None):
+                 factors: np.ndarray | None = None, fft: bool = False):
         self.ctx = ctx
         self.N = int(N)
         self.precision = _precision(precision)
         h = C.c_void_p()
         lib = load()
-        if factors is None:
+        if fft:
+            if self.precision != KP_FP64 or factors is not None:
+                raise ValueError("the FFT preconditioner is FP64 and takes no factors")
+            check(lib.build_preconditioner_fft(ctx.handle, self.N, C.byref(h)))
+            self.info = {"rank": 0, "rho_min": 1.0, "rho_max": 1.0, "fft": True}
+        elif factors is None:
             info = PrecondInfo()
             check(lib.build_preconditioner(ctx.handle, self.N, float(eps), int(rank), self.precision,
                                            C.byref(h), C.byref(info)))

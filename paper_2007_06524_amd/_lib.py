@@ -81,6 +81,7 @@ SIGNATURES = {
     "kp_coeff_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "setup_coeff": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                               C.POINTER(C.c_void_p)]),
+    "build_preconditioner_fft": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     "setup_coeff_inclusions": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double,
                                          C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_void_p)]),
     "kp_coeff_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

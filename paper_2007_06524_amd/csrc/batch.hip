@@ -247,6 +247,8 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
   for (Group& g : B.groups) {
     if ((preconds[g.inst[0]]->precision == KP_MIXED_FP16) != B.fp16)
       return fail(KP_ERR_STATE, "pcg_solve_batched: BF16 and FP16 preconditioners in one batch");
+    if (g.pc->fft)
+      return fail(KP_ERR_STATE, "pcg_solve_batched: the FFT preconditioner is for single solves");
     g.N = g.pc->N;
     g.n3 = (size_t)g.N * g.N * g.N;
     g.nsys = 3 * (int)g.inst.size();

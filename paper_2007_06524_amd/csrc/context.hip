@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <hipfft/hipfft.h>
+
 #include "kp_internal.h"
 
 namespace kp {
@@ -590,6 +592,10 @@ int kp_free_precond(kp_precond* pc) {
   dev_free(ctx, pc->c2_16);
   dev_free(ctx, pc->b3_16);
   for (int l = 0; l < 3; ++l) dev_free(ctx, pc->circ16[l]);
+  if (pc->fft_fwd) hipfftDestroy((hipfftHandle)pc->fft_fwd);
+  if (pc->fft_inv) hipfftDestroy((hipfftHandle)pc->fft_inv);
+  dev_free(ctx, pc->fft_sym);
+  dev_free(ctx, pc->fft_work);
   delete pc;
   return KP_OK;
 }

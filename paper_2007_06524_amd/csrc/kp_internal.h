@@ -195,6 +195,14 @@ struct kp_precond {
   int tile[3] = {-1, -1, -1};   // tile configuration per GEMM stage (-1: size heuristic)
   int tile_batch[3] = {-1, -1, -1};  // the same, tuned for batched solves
   int tuned_nsys = 0;                // batch size tile_batch was tuned for (0: not tuned)
+  // FFT-diagonalized exact preconditioner (build_preconditioner_fft; R = 0):
+  // hipFFT plans of the N^3 real <-> half-spectrum transforms, the symbol
+  // g(k) / N^3 on the half spectrum N x N x (N/2+1), and the complex work array.
+  int fft = 0;
+  void* fft_fwd = nullptr;   // hipfftHandle, D2Z
+  void* fft_inv = nullptr;   // hipfftHandle, Z2D
+  double* fft_sym = nullptr;
+  void* fft_work = nullptr;
 };
 
 namespace kp {
@@ -261,7 +269,10 @@ int launch_resid_f64_to_f32(kp_context* ctx, const double* x, const double* cell
 int launch_finalize(kp_context* ctx, const double* partial, int nparts, int nvals, int mode,
                     Scalars* s, size_t n3, int nsys = 1);
 
-// Preconditioner: z = sum_k (C1 x C2 x C3) x for x in the precision's input type.
+// z = F^-1 (g F r) with the exact symbol (pc->fft), one system.
+int launch_precond_fft(kp_context* ctx, const kp_precond* pc, const double* r, double* z);
+// Preconditioner: z = sum_k (C1 x C2 x C3) x for x in the precision's input type
+// (FP64: or the FFT preconditioner when pc->fft).
 // tiles: the tile configuration per stage (NULL: the preconditioner's own).
 int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, double* z,
                        const Scalars* s, const Batch& bt = Batch(), void* T = nullptr,

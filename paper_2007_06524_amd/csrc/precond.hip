@@ -1026,6 +1026,10 @@ int run_stages(kp_context* ctx, const Stages& st, const int* tiles, F&& run) {
 
 int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, double* z,
                        const Scalars* s, const Batch& bt, void* T, void* U, const int* tiles) {
+  if (pc->fft) {
+    if (bt.nsys != 1) return fail(KP_ERR_STATE, "the FFT preconditioner applies to one system at a time");
+    return launch_precond_fft(ctx, pc, x, z);
+  }
   const size_t n3 = (size_t)pc->N * pc->N * pc->N;
   if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(double), &T));
   if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(double), &U));
@@ -1072,6 +1076,10 @@ int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, fl
 // T, U and X are zero-filled first.
 int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_tile_timing* table,
                      int cap, int* count, int* tiles, void* T, void* U, void* X, void* Z) {
+  if (pc->fft) {  // no GEMM tiles to choose
+    if (count) *count = 0;
+    return KP_OK;
+  }
   const size_t n3 = (size_t)pc->N * pc->N * pc->N;
   const bool sixteen = pc->precision != KP_FP64;
   const size_t el = sixteen ? sizeof(bf16_t) : sizeof(double);
