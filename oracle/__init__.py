@@ -21,6 +21,9 @@ Modules
   pcg        textbook preconditioned CG on the zero-mean subspace (eq. DD_Eqn)
   homogenize homogenized matrix (eq. Ahom3_m_entry_comp) and its energy form
   dense      brute-force dense solve for tiny grids
+  twod       the same discretization, solve, homogenized matrix and rank-R
+             preconditioner with d = 2 (eqs. As_Kron, DiagFLaplace2D,
+             Lap2DtimesX)
 
 Parity status: every function is pinned by a test under tests/ against facts
 the paper or the mathematics fix (worked matrices, closed forms, invariants,
