@@ -319,6 +319,50 @@ int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* const* coeffs
                       const kp_precond* const* preconds, double* const* x_dev,
                       const kp_solve_opts* opts, kp_solve_stats* stats, double* ahom);
 
+/* ---- the two-dimensional problem (d = 2; Table 2) ------------------------ */
+
+/* The same solver for the periodic 2D problem -div(a grad u) = f on the unit
+ * square: an L x L lattice of cells, N = n0 L nodes per axis, fields of N^2
+ * doubles [i1][i2].  The stiffness is the Kronecker sum of eq. As_Kron (a
+ * 5-point stencil whose edge weight is the mean of the coefficient over the
+ * two voxels sharing the edge), the corrector right-hand sides are
+ * f_i(p) = h (w_i(p) - w_i(p - e_i)) (A = h^(d-2) K = K), i = 1, 2, and
+ * a_hom is 2 x 2: delta_ij mean(a) - sum_p phi_i(p) f_j(p).
+ * A 2D coefficient or preconditioner works with pcg_solve (rhs 0..2; with a
+ * 2D preconditioner of the same N), kp_stiffness_apply, kp_precond_apply,
+ * kp_coeff_fields (2 N^2 doubles each), kp_coeff_update (L^2 cells) and
+ * kp_homogenized_matrix (phi_dev[0..1], ahom: 4 doubles row-major); the
+ * batched solver, the Monte-Carlo driver and the FFT preconditioner are 3D
+ * only (KP_ERR_STATE). */
+
+/* 2D coefficient: a_cell host, L^2 doubles [c1][c2]; incl and background as
+ * setup_coeff_inclusions (incl = n0: whole cells). */
+int setup_coeff_2d(kp_context* ctx, int L, int n0, int incl, double background, const double* a_cell,
+                   int precision, kp_coeff** out);
+
+/* Rank-R factors of the 2D preconditioner symbol 1 / (mu_k1 + mu_k2) (eq.
+ * DiagFLaplace2D; the 2D decomposition before eq. Lap2DtimesX), host only.
+ * In 2D the Tucker and canonical forms coincide with the truncated
+ * eigen-expansion of the symbol matrix: the symbol is weighted to relative
+ * form (s s^T * G+, s_i = sqrt(mu_i + mu_1), zero mode set to 1/mu_1), reduced
+ * to its N/2 + 1 distinct indices (it is even), and its leading eigenpairs by
+ * |lambda| give u1 = sqrt|lambda| z / s and u2 = sign(lambda) u1.  rank = 0
+ * selects the smallest R with relative Frobenius error <= eps (at most 16).
+ * factors_out: 2 R N doubles [mode][k][i].  info as kp_lowrank_factors
+ * (cp_rel_err = the truncation error, tucker_rank = R).  Errors: KP_ERR_ARG,
+ * KP_ERR_PRECOND_INDEFINITE if rho_min <= 0. */
+int kp_lowrank_factors_2d(int N, double eps, int rank, double* factors_out, size_t capacity,
+                          kp_precond_info* info);
+
+/* 2D preconditioner z = sum_k C1^k X (C2^k)^T (eq. Lap2DtimesX with dense
+ * circulants), applied as two MFMA GEMM stages (the 3D stages (ii) and (iii)
+ * without the third mode).  As build_preconditioner / kp_precond_from_factors
+ * (factors: 2 R N doubles, each even). */
+int build_preconditioner_2d(kp_context* ctx, int N, double eps, int rank, int precision,
+                            kp_precond** out, kp_precond_info* info);
+int kp_precond_from_factors_2d(kp_context* ctx, int N, int R, const double* factors, int precision,
+                               kp_precond** out);
+
 /* ---- Monte-Carlo statistics (Section 5.3) ------------------------------- */
 
 typedef struct {

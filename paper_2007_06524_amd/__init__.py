@@ -24,7 +24,7 @@ from ._lib import (KP_FP64, KP_MIXED_BF16, KP_MIXED_FP16, KP_NOT_CONVERGED, KP_O
                    check, load)
 
 __all__ = ["Context", "Coeff", "Precond", "solve", "solve_batched", "homogenized_matrix", "stiffness_apply",
-           "lowrank_factors", "mc_homogenize", "KronPCGError", "PRECISIONS", "KP_FP64", "KP_MIXED_BF16",
+           "lowrank_factors", "lowrank_factors_2d", "mc_homogenize", "KronPCGError", "PRECISIONS", "KP_FP64", "KP_MIXED_BF16",
            "KP_MIXED_FP16", "KP_OK", "KP_NOT_CONVERGED", "KP_WARN_RHS_MEAN"]
 
 _live_contexts = weakref.WeakSet()
@@ -117,18 +117,19 @@ class Coeff:
     def __init__(self, ctx: Context, cells: np.ndarray, n0: int, precision="fp64",
                  inclusion: int | None = None, background: float | None = None):
         cells = np.ascontiguousarray(cells, dtype=np.float64)
-        if cells.ndim != 3 or len(set(cells.shape)) != 1:
-            raise ValueError("cells must be an (L, L, L) array")
+        if cells.ndim not in (2, 3) or len(set(cells.shape)) != 1:
+            raise ValueError("cells must be an (L, L, L) array, or (L, L) for the 2D problem")
         self.ctx = ctx
+        self.dim = cells.ndim
         self.L = cells.shape[0]
         self.n0 = int(n0)
         self.precision = _precision(precision)
         self.inclusion = self.n0 if inclusion is None else int(inclusion)
         self.background = 0.0 if background is None else float(background)
         h = C.c_void_p()
-        check(load().setup_coeff_inclusions(ctx.handle, self.L, self.n0, self.inclusion, self.background,
-                                            cells.ctypes.data_as(C.POINTER(C.c_double)), self.precision,
-                                            C.byref(h)))
+        setup = load().setup_coeff_2d if self.dim == 2 else load().setup_coeff_inclusions
+        check(setup(ctx.handle, self.L, self.n0, self.inclusion, self.background,
+                    cells.ctypes.data_as(C.POINTER(C.c_double)), self.precision, C.byref(h)))
         self.handle = h
         self.N = self.L * self.n0
         ctx._owned.append(self)
@@ -136,15 +137,15 @@ class Coeff:
     def update(self, cells_dev):
         """Re-assemble from a new realization already on the device (float64 (L, L, L))."""
         import torch
-        if tuple(cells_dev.shape) != (self.L,) * 3:
-            raise ValueError("cells_dev must have shape (L, L, L)")
+        if tuple(cells_dev.shape) != (self.L,) * self.dim:
+            raise ValueError("cells_dev must have shape (L,) * dim")
         check(load().kp_coeff_update(self.ctx.handle, self.handle, _ptr(cells_dev)))
 
     def fields(self):
-        """(w, f): torch float64 tensors of shape (3, N, N, N)."""
+        """(w, f): torch float64 tensors of shape (d, N, ..., N) (d = 3 or 2)."""
         import torch
         N = self.N
-        w = torch.empty((3, N, N, N), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        w = torch.empty((self.dim,) + (N,) * self.dim, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
         f = torch.empty_like(w)
         check(load().kp_coeff_fields(self.ctx.handle, self.handle, _ptr(w), _ptr(f)))
         return w, f
@@ -162,13 +163,30 @@ class Precond:
     fft=True the exact FFT-diagonalized one (build_preconditioner_fft, FP64)."""
 
     def __init__(self, ctx: Context, N: int, eps: float = 1e-3, rank: int = 0, precision="fp64",
-                 factors: np.ndarray | None = None, fft: bool = False):
+                 factors: np.ndarray | None = None, fft: bool = False, dim: int = 3):
         self.ctx = ctx
         self.N = int(N)
+        self.dim = int(dim)
         self.precision = _precision(precision)
         h = C.c_void_p()
         lib = load()
-        if fft:
+        if self.dim == 2:
+            if fft:
+                raise ValueError("the FFT preconditioner is 3D")
+            if factors is None:
+                info = PrecondInfo()
+                check(lib.build_preconditioner_2d(ctx.handle, self.N, float(eps), int(rank), self.precision,
+                                                  C.byref(h), C.byref(info)))
+                self.info = info.as_dict()
+            else:
+                F = np.ascontiguousarray(factors, dtype=np.float64)
+                if F.ndim != 3 or F.shape[0] != 2 or F.shape[2] != self.N:
+                    raise ValueError("2D factors must have shape (2, R, N)")
+                check(lib.kp_precond_from_factors_2d(ctx.handle, self.N, F.shape[1],
+                                                     F.ctypes.data_as(C.POINTER(C.c_double)), self.precision,
+                                                     C.byref(h)))
+                self.info = {"rank": F.shape[1]}
+        elif fft:
             if self.precision != KP_FP64 or factors is not None:
                 raise ValueError("the FFT preconditioner is FP64 and takes no factors")
             check(lib.build_preconditioner_fft(ctx.handle, self.N, C.byref(h)))
@@ -245,7 +263,7 @@ def solve(ctx: Context, coeff: Coeff, precond: Precond, rhs: int = 1, f=None, x=
     import torch
     N = coeff.N
     if x is None:
-        x = torch.empty((N, N, N), dtype=torch.float64, device=f"cuda:{ctx.device}")
+        x = torch.empty((N,) * coeff.dim, dtype=torch.float64, device=f"cuda:{ctx.device}")
     if replace_every is None:
         replace_every = 0 if coeff.precision == KP_FP64 else 25
     opts = SolveOpts(float(tol), int(maxit), int(replace_every), int(bool(use_x0)), int(check_every))
@@ -316,11 +334,23 @@ def mc_homogenize(ctx: Context, cells, n0: int, pc: Precond, inclusion: int | No
 
 
 def homogenized_matrix(ctx: Context, coeff: Coeff, phis) -> np.ndarray:
-    """kp_homogenized_matrix: 3x3 numpy array from the three corrector solutions."""
-    arr = (C.c_void_p * 3)(*[_ptr(p).value for p in phis])
+    """kp_homogenized_matrix: d x d numpy array from the d corrector solutions."""
+    d = coeff.dim
+    arr = (C.c_void_p * 3)(*([_ptr(p).value for p in phis[:d]] + [None] * (3 - d)))
     out = (C.c_double * 9)()
     check(load().kp_homogenized_matrix(ctx.handle, coeff.handle, arr, out))
-    return np.array(list(out)).reshape(3, 3)
+    return np.array(list(out)[:d * d]).reshape(d, d)
+
+
+def lowrank_factors_2d(N: int, eps: float = 1e-3, rank: int = 0):
+    """kp_lowrank_factors_2d (host only): factors (2, R, N) and the report."""
+    cap = 2 * 16 * N
+    buf = (C.c_double * cap)()
+    info = PrecondInfo()
+    check(load().kp_lowrank_factors_2d(int(N), float(eps), int(rank), buf, cap, C.byref(info)))
+    R = info.rank
+    F = np.frombuffer(buf, dtype=np.float64, count=2 * R * N).reshape(2, R, N).copy()
+    return F, info.as_dict()
 
 
 def lowrank_factors(N: int, eps: float = 1e-3, rank: int = 0):

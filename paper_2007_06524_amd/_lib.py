@@ -82,6 +82,14 @@ SIGNATURES = {
     "setup_coeff": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                               C.POINTER(C.c_void_p)]),
     "build_preconditioner_fft": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+    "setup_coeff_2d": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double),
+                                 C.c_int, C.POINTER(C.c_void_p)]),
+    "kp_lowrank_factors_2d": (C.c_int, [C.c_int, C.c_double, C.c_int, C.POINTER(C.c_double), C.c_size_t,
+                                        C.POINTER(PrecondInfo)]),
+    "build_preconditioner_2d": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int,
+                                          C.POINTER(C.c_void_p), C.POINTER(PrecondInfo)]),
+    "kp_precond_from_factors_2d": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
+                                             C.POINTER(C.c_void_p)]),
     "setup_coeff_inclusions": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double,
                                          C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_void_p)]),
     "kp_coeff_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

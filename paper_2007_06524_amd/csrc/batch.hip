@@ -249,6 +249,8 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
       return fail(KP_ERR_STATE, "pcg_solve_batched: BF16 and FP16 preconditioners in one batch");
     if (g.pc->fft)
       return fail(KP_ERR_STATE, "pcg_solve_batched: the FFT preconditioner is for single solves");
+    if (g.pc->dim != 3 || coeffs[g.inst[0]]->dim != 3)
+      return fail(KP_ERR_STATE, "pcg_solve_batched: 2D problems are solved one at a time (pcg_solve)");
     g.N = g.pc->N;
     g.n3 = (size_t)g.N * g.N * g.N;
     g.nsys = 3 * (int)g.inst.size();

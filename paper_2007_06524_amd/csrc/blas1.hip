@@ -500,6 +500,8 @@ struct PhiPtrs {
   const double* p[3];
 };
 
+// <phi_a, f_b> for a, b < D (value 3 a + b; the others stay 0) and the cell sum (value 9).
+template <int D>
 __global__ __launch_bounds__(256) void k_multidot9(PhiPtrs phi, const double* __restrict__ f,
                                                    size_t n, const double* __restrict__ cells,
                                                    size_t ncells, double* __restrict__ partial) {
@@ -507,13 +509,14 @@ __global__ __launch_bounds__(256) void k_multidot9(PhiPtrs phi, const double* __
 #pragma unroll
   for (int k = 0; k < 10; ++k) acc[k] = 0.0;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const double f0 = f[i], f1 = f[n + i], f2 = f[2 * n + i];
+    double fb[D];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < D; ++b) fb[b] = f[b * n + i];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
       const double v = phi.p[a][i];
-      acc[3 * a + 0] += v * f0;
-      acc[3 * a + 1] += v * f1;
-      acc[3 * a + 2] += v * f2;
+#pragma unroll
+      for (int b = 0; b < D; ++b) acc[3 * a + b] += v * fb[b];
     }
   }
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < ncells; i += (size_t)gridDim.x * 256)
@@ -683,13 +686,15 @@ int launch_count_active(kp_context* ctx, const Scalars* s, int nsys, int* out) {
 }
 
 int launch_multidot9(kp_context* ctx, const double* const* phi, const double* f, size_t n,
-                     const double* cells, size_t ncells, double* partial, int* nparts) {
+                     const double* cells, size_t ncells, double* partial, int* nparts, int d) {
   ScopedTimer tm(ctx, KP_TIMER_VECTOR);
   PhiPtrs pp;
-  for (int a = 0; a < 3; ++a) pp.p[a] = phi[a];
+  for (int a = 0; a < 3; ++a) pp.p[a] = a < d ? phi[a] : nullptr;
   const int g = kRedBlocks;
-  hipLaunchKernelGGL(k_multidot9, dim3(g), dim3(256), 0, ctx->stream, pp, f, n, cells, ncells,
-                     partial);
+  if (d == 2)
+    hipLaunchKernelGGL(k_multidot9<2>, dim3(g), dim3(256), 0, ctx->stream, pp, f, n, cells, ncells, partial);
+  else
+    hipLaunchKernelGGL(k_multidot9<3>, dim3(g), dim3(256), 0, ctx->stream, pp, f, n, cells, ncells, partial);
   KP_HIP(hipGetLastError());
   *nparts = g;
   return KP_OK;

@@ -30,7 +30,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // bg + frac (mean cell value - bg).
 __global__ __launch_bounds__(256) void k_ahom_final(const double* __restrict__ partial, int nparts,
                                                     double ncells, double h, int sub, double frac,
-                                                    double bg, double* __restrict__ out) {
+                                                    double bg, int d, double* __restrict__ out) {
   __shared__ double tot[10];
   __shared__ double red[4];
   for (int v = 0; v < 10; ++v) {
@@ -42,11 +42,12 @@ __global__ __launch_bounds__(256) void k_ahom_final(const double* __restrict__ p
     if (threadIdx.x == 0) tot[v] = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
   }
-  if (threadIdx.x < 9) {
-    const int i = threadIdx.x / 3, j = threadIdx.x % 3;
+  // d x d entries, row-major; the lumped integral carries h^(d-2).
+  if (threadIdx.x < d * d) {
+    const int i = threadIdx.x / d, j = threadIdx.x % d;
     const double mc = tot[9] / ncells;
     const double mean = sub ? bg + frac * (mc - bg) : mc;
-    out[threadIdx.x] = (i == j ? mean : 0.0) - h * tot[threadIdx.x];
+    out[threadIdx.x] = (i == j ? mean : 0.0) - h * tot[3 * i + j];
   }
 }
 
@@ -169,12 +170,13 @@ int ws_get(kp_context* ctx, int slot, size_t bytes, void** ptr) {
 }
 
 // Canonical factors [l][k][i] -> dense circulant operands of the three GEMMs.
+// modes = 3, or 2 for the 2D preconditioner (factors of C1 and C2 only; no b3).
 static int upload_precond(kp_context* ctx, int N, int R, const double* factors, int precision,
-                          kp_precond** out) {
+                          kp_precond** out, int modes = 3) {
   const size_t n = N, RN = (size_t)R * N;
   // First column of each circulant: c[d] = (1/N) sum_j u(j) cos(2 pi j d / N).
   std::vector<double> col((size_t)3 * R * N);
-  for (int l = 0; l < 3; ++l)
+  for (int l = 0; l < modes; ++l)
     for (int k = 0; k < R; ++k) {
       const double* u = factors + ((size_t)l * R + k) * n;
       double* c = col.data() + ((size_t)l * R + k) * n;
@@ -190,19 +192,21 @@ static int upload_precond(kp_context* ctx, int N, int R, const double* factors, 
   auto C = [&](int l, int k, int a, int b) {
     return col[((size_t)l * R + k) * n + (size_t)((a - b + N) % N)];
   };
-  std::vector<double> a1(n * RN), c2(RN * n), b3(RN * n);
+  std::vector<double> a1(n * RN), c2(RN * n), b3(modes == 3 ? RN * n : 0);
   for (int j1 = 0; j1 < N; ++j1)
     for (int k = 0; k < R; ++k)
       for (int i1 = 0; i1 < N; ++i1) a1[(size_t)j1 * RN + (size_t)k * n + i1] = C(0, k, j1, i1);
   for (int k = 0; k < R; ++k)
     for (int j2 = 0; j2 < N; ++j2)
       for (int i2 = 0; i2 < N; ++i2) c2[((size_t)k * n + j2) * n + i2] = C(1, k, j2, i2);
-  for (int k = 0; k < R; ++k)
-    for (int j3 = 0; j3 < N; ++j3)
-      for (int i3 = 0; i3 < N; ++i3) b3[((size_t)k * n + j3) * n + i3] = C(2, k, j3, i3);
+  if (modes == 3)
+    for (int k = 0; k < R; ++k)
+      for (int j3 = 0; j3 < N; ++j3)
+        for (int i3 = 0; i3 < N; ++i3) b3[((size_t)k * n + j3) * n + i3] = C(2, k, j3, i3);
 
   kp_precond* pc = new kp_precond();
   pc->ctx = ctx;
+  pc->dim = modes;
   pc->N = N;
   pc->R = R;
   pc->precision = precision;
@@ -210,14 +214,15 @@ static int upload_precond(kp_context* ctx, int N, int R, const double* factors, 
   int st = KP_OK;
   if ((st = dev_alloc(ctx, (void**)&pc->a1_64, bytes)) < 0 ||
       (st = dev_alloc(ctx, (void**)&pc->c2_64, bytes)) < 0 ||
-      (st = dev_alloc(ctx, (void**)&pc->b3_64, bytes)) < 0) {
+      (modes == 3 && (st = dev_alloc(ctx, (void**)&pc->b3_64, bytes)) < 0)) {
     kp_free_precond(pc);
     return st;
   }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpyAsync(pc->a1_64, a1.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(pc->c2_64, c2.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(pc->b3_64, b3.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && modes == 3)
+    e = hipMemcpyAsync(pc->b3_64, b3.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess && precision != KP_FP64) {
     // Each 16-bit row is (hi | lo): hi = round(c), lo = round(c - hi).  A single
     // rounding perturbs the symbol of every circulant by ~2^-9 max|u| at all
@@ -250,12 +255,12 @@ static int upload_precond(kp_context* ctx, int N, int R, const double* factors, 
     std::vector<uint16_t> h1, h2, h3;
     split_rows(a1, n, RN, h1);
     split_rows(c2, RN, n, h2);
-    split_rows(b3, RN, n, h3);
+    if (modes == 3) split_rows(b3, RN, n, h3);
     const size_t b16 = 2 * n * RN * sizeof(uint16_t);
     // Shifted reversed first columns (see kp_precond::circ16), same hi / lo values.
     const size_t np8 = n + 8, per_k = 2 * 8 * np8;
     std::vector<uint16_t> hc[3];
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 0; l < modes; ++l) {
       hc[l].assign((size_t)R * per_k, 0);
       for (int k = 0; k < R; ++k)
         for (int sft = 0; sft < 8; ++sft)
@@ -270,17 +275,18 @@ static int upload_precond(kp_context* ctx, int N, int R, const double* factors, 
     const size_t bc = (size_t)R * per_k * sizeof(uint16_t);
     if ((st = dev_alloc(ctx, (void**)&pc->a1_16, b16)) < 0 ||
         (st = dev_alloc(ctx, (void**)&pc->c2_16, b16)) < 0 ||
-        (st = dev_alloc(ctx, (void**)&pc->b3_16, b16)) < 0 ||
+        (modes == 3 && (st = dev_alloc(ctx, (void**)&pc->b3_16, b16)) < 0) ||
         (st = dev_alloc(ctx, (void**)&pc->circ16[0], bc)) < 0 ||
         (st = dev_alloc(ctx, (void**)&pc->circ16[1], bc)) < 0 ||
-        (st = dev_alloc(ctx, (void**)&pc->circ16[2], bc)) < 0) {
+        (modes == 3 && (st = dev_alloc(ctx, (void**)&pc->circ16[2], bc)) < 0)) {
       kp_free_precond(pc);
       return st;
     }
     e = hipMemcpyAsync(pc->a1_16, h1.data(), b16, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(pc->c2_16, h2.data(), b16, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(pc->b3_16, h3.data(), b16, hipMemcpyHostToDevice, ctx->stream);
-    for (int l = 0; l < 3 && e == hipSuccess; ++l)
+    if (e == hipSuccess && modes == 3)
+      e = hipMemcpyAsync(pc->b3_16, h3.data(), b16, hipMemcpyHostToDevice, ctx->stream);
+    for (int l = 0; l < modes && e == hipSuccess; ++l)
       e = hipMemcpyAsync(pc->circ16[l], hc[l].data(), bc, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // host staging goes out of scope
   }
@@ -295,14 +301,16 @@ static int upload_precond(kp_context* ctx, int N, int R, const double* factors, 
 
 int launch_ahom(kp_context* ctx, const kp_coeff* c, const double* const* phi, double* part,
                 double* out) {
-  const size_t n3 = (size_t)c->N * c->N * c->N;
-  const size_t nc = (size_t)c->L * c->L * c->L;
+  const size_t n3 = unknowns(c->N, c->dim);
+  const size_t nc = unknowns(c->L, c->dim);
   int np = 0;
-  KP_TRY(launch_multidot9(ctx, phi, c->f, n3, c->cells, nc, part, &np));
+  KP_TRY(launch_multidot9(ctx, phi, c->f, n3, c->cells, nc, part, &np, c->dim));
   const CellGeom cg = geom_of(c);
   const double fr = (double)c->incl / c->n0;
+  const double frac = c->dim == 2 ? fr * fr : fr * fr * fr;
+  const double hfac = c->dim == 2 ? 1.0 : 1.0 / c->N;  // h^(d-2)
   hipLaunchKernelGGL(k_ahom_final, dim3(1), dim3(256), 0, ctx->stream, (const double*)part, np,
-                     (double)nc, 1.0 / c->N, (int)cg.sub(), fr * fr * fr, c->bg, out);
+                     (double)nc, hfac, (int)cg.sub(), frac, c->bg, c->dim, out);
   KP_HIP(hipGetLastError());
   return KP_OK;
 }
@@ -398,7 +406,7 @@ int kp_context_read_timing(kp_context* ctx, double* ms, long long* launches) {
 int kp_coeff_update(kp_context* ctx, kp_coeff* c, const double* a_cell_dev) {
   if (!ctx || !c || !a_cell_dev) return fail(KP_ERR_ARG, "kp_coeff_update: NULL argument");
   if (c->ctx != ctx) return fail(KP_ERR_STATE, "kp_coeff_update: coefficient of another context");
-  const size_t nc = (size_t)c->L * c->L * c->L;
+  const size_t nc = unknowns(c->L, c->dim);
   void* flag;
   KP_TRY(ws_get(ctx, WS_FLAG, sizeof(int), &flag));
   KP_HIP(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
@@ -411,8 +419,9 @@ int kp_coeff_update(kp_context* ctx, kp_coeff* c, const double* a_cell_dev) {
   return launch_assemble(ctx, c);
 }
 
-int setup_coeff_inclusions(kp_context* ctx, int L, int n0, int incl, double background,
-                           const double* a_cell, int precision, kp_coeff** out) {
+namespace {
+int setup_coeff_dim(kp_context* ctx, int dim, int L, int n0, int incl, double background,
+                    const double* a_cell, int precision, kp_coeff** out) {
   if (!ctx || !a_cell || !out) return fail(KP_ERR_ARG, "setup_coeff: NULL argument");
   *out = nullptr;
   if (!valid_precision(precision)) return fail(KP_ERR_ARG, "setup_coeff: bad precision %d", precision);
@@ -423,7 +432,7 @@ int setup_coeff_inclusions(kp_context* ctx, int L, int n0, int incl, double back
   if (incl < n0 && (!std::isfinite(background) || !(background > 0.0)))
     return fail(KP_ERR_ARG, "setup_coeff: background %g must be finite and > 0", background);
   const int N = L * n0;
-  const size_t nc = (size_t)L * L * L;
+  const size_t nc = unknowns(L, dim);
   for (size_t i = 0; i < nc; ++i) {
     if (!std::isfinite(a_cell[i]) || !(a_cell[i] > 0.0))
       return fail(KP_ERR_ARG, "setup_coeff: cell %zu has value %g (must be finite and > 0)", i, a_cell[i]);
@@ -431,17 +440,18 @@ int setup_coeff_inclusions(kp_context* ctx, int L, int n0, int incl, double back
   KP_HIP(hipSetDevice(ctx->device));
   kp_coeff* c = new kp_coeff();
   c->ctx = ctx;
+  c->dim = dim;
   c->L = L;
   c->n0 = n0;
   c->N = N;
   c->incl = incl;
   c->bg = incl < n0 ? background : 0.0;
   c->precision = precision;
-  const size_t n3 = (size_t)N * N * N;
+  const size_t n3 = unknowns(N, dim);
   int st;
   if ((st = dev_alloc(ctx, (void**)&c->cells, nc * sizeof(double))) < 0 ||
-      (st = dev_alloc(ctx, (void**)&c->w64, 3 * n3 * sizeof(double))) < 0 ||
-      (st = dev_alloc(ctx, (void**)&c->f, 3 * n3 * sizeof(double))) < 0 ||
+      (st = dev_alloc(ctx, (void**)&c->w64, dim * n3 * sizeof(double))) < 0 ||
+      (st = dev_alloc(ctx, (void**)&c->f, dim * n3 * sizeof(double))) < 0 ||
       (precision != KP_FP64 && (st = dev_alloc(ctx, (void**)&c->cells32, nc * sizeof(float))) < 0)) {
     kp_free_coeff(c);
     return st;
@@ -459,17 +469,28 @@ int setup_coeff_inclusions(kp_context* ctx, int L, int n0, int incl, double back
   *out = c;
   return KP_OK;
 }
+}  // namespace
+
+int setup_coeff_inclusions(kp_context* ctx, int L, int n0, int incl, double background,
+                           const double* a_cell, int precision, kp_coeff** out) {
+  return setup_coeff_dim(ctx, 3, L, n0, incl, background, a_cell, precision, out);
+}
 
 int setup_coeff(kp_context* ctx, int L, int n0, const double* a_cell, int precision,
                 kp_coeff** out) {
-  return setup_coeff_inclusions(ctx, L, n0, n0, 0.0, a_cell, precision, out);
+  return setup_coeff_dim(ctx, 3, L, n0, n0, 0.0, a_cell, precision, out);
+}
+
+int setup_coeff_2d(kp_context* ctx, int L, int n0, int incl, double background, const double* a_cell,
+                   int precision, kp_coeff** out) {
+  return setup_coeff_dim(ctx, 2, L, n0, incl, background, a_cell, precision, out);
 }
 
 int kp_coeff_size(const kp_coeff* c) { return c ? c->N : -1; }
 
 int kp_coeff_fields(kp_context* ctx, const kp_coeff* c, double* w_dev, double* f_dev) {
   if (!ctx || !c) return fail(KP_ERR_ARG, "kp_coeff_fields: NULL argument");
-  const size_t bytes = 3 * (size_t)c->N * c->N * c->N * sizeof(double);
+  const size_t bytes = c->dim * unknowns(c->N, c->dim) * sizeof(double);
   if (w_dev) KP_HIP(hipMemcpyAsync(w_dev, c->w64, bytes, hipMemcpyDeviceToDevice, ctx->stream));
   if (f_dev) KP_HIP(hipMemcpyAsync(f_dev, c->f, bytes, hipMemcpyDeviceToDevice, ctx->stream));
   return KP_OK;
@@ -494,7 +515,7 @@ int kp_stiffness_apply(kp_context* ctx, const kp_coeff* c, int precision, const 
   if (precision != KP_FP64 && !c->cells32)
     return fail(KP_ERR_STATE, "kp_stiffness_apply: coefficient was set up without float cells");
   const int N = c->N;
-  const size_t n3 = (size_t)N * N * N;
+  const size_t n3 = unknowns(N, c->dim);
   void* part;
   KP_TRY(ws_get(ctx, WS_PART, (size_t)kMaxPartials * 8 * sizeof(double), &part));
   int np = 0;
@@ -552,6 +573,48 @@ int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors
   return KP_OK;
 }
 
+int build_preconditioner_2d(kp_context* ctx, int N, double eps, int rank, int precision,
+                            kp_precond** out, kp_precond_info* info) {
+  if (!ctx || !out) return fail(KP_ERR_ARG, "build_preconditioner_2d: NULL argument");
+  *out = nullptr;
+  if (!valid_precision(precision)) return fail(KP_ERR_ARG, "build_preconditioner_2d: bad precision");
+  if (N < 2 || N > 2048) return fail(KP_ERR_ARG, "build_preconditioner_2d: N = %d out of range", N);
+  KP_HIP(hipSetDevice(ctx->device));
+  std::vector<double> fac((size_t)2 * 16 * N);
+  kp_precond_info inf{};
+  KP_TRY(kp_lowrank_factors_2d(N, eps, rank, fac.data(), fac.size(), &inf));
+  kp_precond* pc = nullptr;
+  KP_TRY(upload_precond(ctx, N, inf.rank, fac.data(), precision, &pc, 2));
+  pc->info = inf;
+  if (info) *info = inf;
+  *out = pc;
+  return KP_OK;
+}
+
+int kp_precond_from_factors_2d(kp_context* ctx, int N, int R, const double* factors, int precision,
+                               kp_precond** out) {
+  if (!ctx || !factors || !out) return fail(KP_ERR_ARG, "kp_precond_from_factors_2d: NULL argument");
+  *out = nullptr;
+  if (!valid_precision(precision)) return fail(KP_ERR_ARG, "kp_precond_from_factors_2d: bad precision");
+  if (N < 2 || N > 2048 || R < 1 || R > 16)
+    return fail(KP_ERR_ARG, "kp_precond_from_factors_2d: need 2 <= N <= 2048 and 1 <= R <= 16");
+  for (int l = 0; l < 2; ++l)
+    for (int k = 0; k < R; ++k)
+      for (int i = 0; i < N; ++i) {
+        const double* u = factors + ((size_t)l * R + k) * N;
+        if (!std::isfinite(u[i])) return fail(KP_ERR_ARG, "kp_precond_from_factors_2d: non-finite factor");
+        const double d = std::fabs(u[i] - u[(N - i) % N]);
+        if (d > 1e-12 * (std::fabs(u[i]) + 1e-300) && d > 0.0)
+          return fail(KP_ERR_ARG, "kp_precond_from_factors_2d: factor (%d,%d) is not even", l, k);
+      }
+  KP_HIP(hipSetDevice(ctx->device));
+  kp_precond* pc = nullptr;
+  KP_TRY(upload_precond(ctx, N, R, factors, precision, &pc, 2));
+  pc->info.rank = R;
+  *out = pc;
+  return KP_OK;
+}
+
 int kp_precond_rank(const kp_precond* pc) { return pc ? pc->R : -1; }
 
 int kp_precond_set_tiles(kp_precond* pc, const int* tiles) {
@@ -602,7 +665,7 @@ int kp_free_precond(kp_precond* pc) {
 
 int kp_precond_apply(kp_context* ctx, const kp_precond* pc, const double* r_dev, double* z_dev) {
   if (!ctx || !pc || !r_dev || !z_dev) return fail(KP_ERR_ARG, "kp_precond_apply: NULL argument");
-  const size_t n3 = (size_t)pc->N * pc->N * pc->N;
+  const size_t n3 = unknowns(pc->N, pc->dim);
   if (pc->precision == KP_FP64) return launch_precond_f64(ctx, pc, r_dev, z_dev, nullptr);
   void *x16, *z32;
   KP_TRY(ws_get(ctx, WS_X16, n3 * sizeof(bf16_t), &x16));
@@ -615,13 +678,14 @@ int kp_precond_apply(kp_context* ctx, const kp_precond* pc, const double* r_dev,
 int kp_homogenized_matrix(kp_context* ctx, const kp_coeff* c, const double* const* phi_dev,
                           double* ahom) {
   if (!ctx || !c || !phi_dev || !ahom) return fail(KP_ERR_ARG, "kp_homogenized_matrix: NULL argument");
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < c->dim; ++i)
     if (!phi_dev[i]) return fail(KP_ERR_ARG, "kp_homogenized_matrix: phi[%d] is NULL", i);
   void *part, *res;
   KP_TRY(ws_get(ctx, WS_PART, (size_t)kMaxPartials * 8 * sizeof(double), &part));
   KP_TRY(ws_get(ctx, WS_SCAL, sizeof(Scalars), &res));
   KP_TRY(launch_ahom(ctx, c, phi_dev, (double*)part, (double*)res));
-  KP_HIP(hipMemcpyAsync(ahom, res, 9 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  KP_HIP(hipMemcpyAsync(ahom, res, (size_t)c->dim * c->dim * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
   KP_HIP(hipStreamSynchronize(ctx->stream));
   return KP_OK;
 }

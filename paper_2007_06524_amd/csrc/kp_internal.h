@@ -162,6 +162,7 @@ void resolve_timers(kp_context* ctx);
 
 struct kp_coeff {
   kp_context* ctx = nullptr;
+  int dim = 3;       // 3, or 2 for the two-dimensional problem
   int L = 0, n0 = 0, N = 0;
   int incl = 0;      // voxels per edge of the centred sub-cell carrying the cell value (n0: whole cell)
   double bg = 0.0;   // coefficient outside the sub-cells (used when incl < n0)
@@ -174,6 +175,7 @@ struct kp_coeff {
 
 struct kp_precond {
   kp_context* ctx = nullptr;
+  int dim = 3;  // 3, or 2: factors of two modes, stages (ii) and (iii) only (no b3)
   int N = 0, R = 0;
   int precision = KP_FP64;
   // Circulant operands of the three NT GEMMs (see precond.hip for the layouts).
@@ -237,10 +239,12 @@ int launch_assemble(kp_context* ctx, kp_coeff* c);
 struct CellGeom {
   int L = 0, n0 = 0, lo = 0, hi = 0;
   double bg = 0.0;
+  int dim = 3;
   bool sub() const { return lo > 0 || hi < n0; }
 };
 inline CellGeom geom_of(const kp_coeff* c) {
   CellGeom g;
+  g.dim = c->dim;
   g.L = c->L;
   g.n0 = c->n0;
   g.lo = (c->n0 - c->incl) / 2;
@@ -335,6 +339,11 @@ int vector_parts(size_t n);
 int launch_ahom(kp_context* ctx, const kp_coeff* c, const double* const* phi, double* part,
                 double* out);
 int launch_multidot9(kp_context* ctx, const double* const* phi, const double* f, size_t n,
-                     const double* cells, size_t ncells, double* partial, int* nparts);
+                     const double* cells, size_t ncells, double* partial, int* nparts, int d = 3);
 
+}  // namespace kp
+
+namespace kp {
+// Unknowns of a coefficient / preconditioner: N^dim.
+inline size_t unknowns(int N, int dim) { return dim == 2 ? (size_t)N * N : (size_t)N * N * N; }
 }  // namespace kp

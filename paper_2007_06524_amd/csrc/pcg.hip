@@ -151,6 +151,10 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   if (rhs == 0 && !f_dev) return fail(KP_ERR_ARG, "pcg_solve: rhs = 0 needs f_dev");
   if (c->ctx != ctx || pc->ctx != ctx) return fail(KP_ERR_STATE, "pcg_solve: handles of another context");
   if (c->N != pc->N) return fail(KP_ERR_STATE, "pcg_solve: coefficient N=%d, preconditioner N=%d", c->N, pc->N);
+  if (c->dim != pc->dim && !pc->fft)
+    return fail(KP_ERR_STATE, "pcg_solve: %dD coefficient with a %dD preconditioner", c->dim, pc->dim);
+  if (pc->fft && c->dim != 3) return fail(KP_ERR_STATE, "pcg_solve: the FFT preconditioner is 3D");
+  if (rhs > c->dim) return fail(KP_ERR_ARG, "pcg_solve: rhs %d of a %dD problem", rhs, c->dim);
   const bool mixed = c->precision != KP_FP64;
   if (mixed != (pc->precision != KP_FP64))
     return fail(KP_ERR_STATE, "pcg_solve: coefficient and preconditioner precisions differ");
@@ -169,7 +173,7 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   S.mixed = mixed;
   S.fp16 = pc->precision == KP_MIXED_FP16;
   S.N = c->N;
-  S.n3 = (size_t)c->N * c->N * c->N;
+  S.n3 = unknowns(c->N, c->dim);
   const size_t vb = S.n3 * (mixed ? sizeof(float) : sizeof(double));
   void *sv, *pv, *fpv;
   KP_TRY(ws_get(ctx, WS_SCAL, sizeof(Scalars), &sv));

@@ -974,6 +974,7 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
 struct Stages {
   GemmArgs s1, s2, s3;
   int nsys, R;
+  int dim = 3;  // 2: no stage (i)
 };
 
 Stages make_stages(int N, int R, const void* x, const void* a1, const void* c2, const void* b3,
@@ -1008,9 +1009,38 @@ Stages make_stages(int N, int R, const void* x, const void* a1, const void* c2, 
   return st;
 }
 
+// d = 2 (eq. Lap2DtimesX): Z = sum_k C1^k X (C2^k)^T as stages (ii) and (iii)
+// of the 3D product without the i3 mode, one system:
+//   (ii)  T[j2][(k,i1)] = sum_i2     C2^k[j2][i2] X[i1][i2]   (batch k, X shared)
+//   (iii) Z[j1][j2]     = sum_(k,i1) C1^k[j1][i1] T[j2][(k,i1)]
+Stages make_stages_2d(int N, int R, const void* x, const void* a1, const void* c2, void* T, void* z,
+                      int planes, const Scalars* s, bool scaled, const bf16_t* const* circ = nullptr) {
+  const long long n = N, nn = n * n, RN = (long long)R * N;
+  const long long p = planes;
+  const long long lo_n = planes == 2 ? n : 0, lo_rn = planes == 2 ? RN : 0;
+  const int* done = s ? &s->done : nullptr;
+  const double* div = (s && scaled) ? &s->x16_scale : nullptr;
+  Stages st;
+  st.nsys = 1;
+  st.R = R;
+  st.dim = 2;
+  st.s2 = gemm_args(c2, x, T, n, n, n, p * n, n, p * nn, 0, OutMap{RN, 0, 1, n, INT_MAX}, done, lo_n,
+                    nullptr, R, R * nn);
+  st.s3 = gemm_args(a1, T, z, n, n, RN, p * RN, RN, 0, R * nn, OutMap{n, 0, 1, 0, INT_MAX}, done,
+                    lo_rn, div, 1, nn);
+  if (circ) {
+    st.s2.circ = circ[1];
+    st.s2.cmode = 1;
+    st.s3.circ = circ[0];
+    st.s3.cmode = 2;
+    st.s2.cn = st.s3.cn = N;
+  }
+  return st;
+}
+
 template <typename F>
 int run_stages(kp_context* ctx, const Stages& st, const int* tiles, F&& run) {
-  {
+  if (st.dim == 3) {
     ScopedTimer tm(ctx, KP_TIMER_GEMM_MODE3);
     KP_TRY(run(0, st.s1, st.nsys, tiles[0]));
   }
@@ -1030,11 +1060,13 @@ int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, d
     if (bt.nsys != 1) return fail(KP_ERR_STATE, "the FFT preconditioner applies to one system at a time");
     return launch_precond_fft(ctx, pc, x, z);
   }
-  const size_t n3 = (size_t)pc->N * pc->N * pc->N;
+  const size_t n3 = unknowns(pc->N, pc->dim);
   if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(double), &T));
-  if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(double), &U));
-  Stages st = make_stages(pc->N, pc->R, x, pc->a1_64, pc->c2_64, pc->b3_64, T, U, z, 1, s, false,
-                          bt.nsys);
+  if (!U && pc->dim == 3) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(double), &U));
+  if (pc->dim == 2 && bt.nsys != 1) return fail(KP_ERR_STATE, "2D preconditioner: one system at a time");
+  Stages st = pc->dim == 2 ? make_stages_2d(pc->N, pc->R, x, pc->a1_64, pc->c2_64, T, z, 1, s, false)
+                           : make_stages(pc->N, pc->R, x, pc->a1_64, pc->c2_64, pc->b3_64, T, U, z, 1, s,
+                                         false, bt.nsys);
   return run_stages(ctx, st, tiles ? tiles : pc->tile,
                     [&](int stage, const GemmArgs& g, int batch, int cfg) {
                       return run_gemm_f64(ctx, g, batch, cfg, stage);
@@ -1044,12 +1076,14 @@ int launch_precond_f64(kp_context* ctx, const kp_precond* pc, const double* x, d
 int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, float* z,
                       const Scalars* s, const Batch& bt, void* T, void* U, const int* tiles,
                       const PrecDots* dots, int* dot_parts) {
-  const size_t n3 = (size_t)pc->N * pc->N * pc->N;
+  const size_t n3 = unknowns(pc->N, pc->dim);
   const bool f16 = pc->precision == KP_MIXED_FP16;
   if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * sizeof(bf16_t), &T));
-  if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(bf16_t), &U));
-  Stages st = make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, 2, s, true,
-                          bt.nsys, pc->circ16);
+  if (!U && pc->dim == 3) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * sizeof(bf16_t), &U));
+  if (pc->dim == 2 && bt.nsys != 1) return fail(KP_ERR_STATE, "2D preconditioner: one system at a time");
+  Stages st = pc->dim == 2 ? make_stages_2d(pc->N, pc->R, x, pc->a1_16, pc->c2_16, T, z, 2, s, true, pc->circ16)
+                           : make_stages(pc->N, pc->R, x, pc->a1_16, pc->c2_16, pc->b3_16, T, U, z, 2, s,
+                                         true, bt.nsys, pc->circ16);
   if (!tiles) tiles = pc->tile;
   if (dot_parts) *dot_parts = 0;
   if (dots) {
@@ -1080,10 +1114,11 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
     if (count) *count = 0;
     return KP_OK;
   }
-  const size_t n3 = (size_t)pc->N * pc->N * pc->N;
+  const size_t n3 = unknowns(pc->N, pc->dim);
   const bool sixteen = pc->precision != KP_FP64;
   const size_t el = sixteen ? sizeof(bf16_t) : sizeof(double);
   if (nsys < 1 || ((!T || !U || !X || !Z) && nsys != 1)) return fail(KP_ERR_ARG, "autotune: bad batch");
+  if (pc->dim == 2 && nsys != 1) return fail(KP_ERR_STATE, "autotune: 2D preconditioners tune one system");
   if (!T) KP_TRY(ws_get(ctx, WS_T, n3 * pc->R * el, &T));
   if (!U) KP_TRY(ws_get(ctx, WS_U, n3 * pc->R * el, &U));
   if (!X) KP_TRY(ws_get(ctx, sixteen ? WS_X16 : WS_TMP64, n3 * el, &X));
@@ -1091,14 +1126,19 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
   KP_HIP(hipMemsetAsync(T, 0, nsys * n3 * pc->R * el, ctx->stream));
   KP_HIP(hipMemsetAsync(U, 0, nsys * n3 * pc->R * el, ctx->stream));
   KP_HIP(hipMemsetAsync(X, 0, nsys * n3 * el, ctx->stream));
-  Stages st = sixteen ? make_stages(pc->N, pc->R, X, pc->a1_16, pc->c2_16, pc->b3_16, T, U, Z, 2,
-                                    nullptr, false, nsys, pc->circ16)
-                      : make_stages(pc->N, pc->R, X, pc->a1_64, pc->c2_64, pc->b3_64, T, U, Z, 1,
-                                    nullptr, false, nsys);
+  Stages st;
+  if (pc->dim == 2)
+    st = sixteen ? make_stages_2d(pc->N, pc->R, X, pc->a1_16, pc->c2_16, T, Z, 2, nullptr, false, pc->circ16)
+                 : make_stages_2d(pc->N, pc->R, X, pc->a1_64, pc->c2_64, T, Z, 1, nullptr, false);
+  else
+    st = sixteen ? make_stages(pc->N, pc->R, X, pc->a1_16, pc->c2_16, pc->b3_16, T, U, Z, 2, nullptr,
+                               false, nsys, pc->circ16)
+                 : make_stages(pc->N, pc->R, X, pc->a1_64, pc->c2_64, pc->b3_64, T, U, Z, 1, nullptr,
+                               false, nsys);
   const bool f16 = pc->precision == KP_MIXED_FP16;
   const int ntile = sixteen ? kTiles16 : kTiles64, ncfg = 2 * ntile;
   int n = 0;
-  for (int stg = 0; stg < 3; ++stg) {
+  for (int stg = pc->dim == 2 ? 1 : 0; stg < 3; ++stg) {
     const GemmArgs& g = stg == 0 ? st.s1 : (stg == 1 ? st.s2 : st.s3);
     const int batch = stg == 1 ? nsys * pc->R : nsys;
     double best = 1e300;

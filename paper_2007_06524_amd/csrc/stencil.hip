@@ -79,6 +79,33 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ cel
   f[2 * n3 + idx] = h * (w2 - w2m);
 }
 
+// d = 2: one thread per node [i1][i2]; the four voxels around p are
+// v = p - 1 + d, d in {0,1}^2, and the weight of the edge (p, p + e_l) is the
+// mean of the two voxels in layer p_l along l (transverse p_t - 1 or p_t).
+__global__ __launch_bounds__(256) void k_assemble2d(const double* __restrict__ cells, int L, int n0,
+                                                    int lo, int hi, double bg, int N, double h,
+                                                    double* __restrict__ w64, double* __restrict__ f) {
+  const size_t n2 = (size_t)N * N;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n2) return;
+  const int p2 = (int)(idx % N), p1 = (int)(idx / N);
+  const int v1[2] = {(p1 + N - 1) % N, p1}, v2[2] = {(p2 + N - 1) % N, p2};
+  double a[2][2];
+  for (int d1 = 0; d1 < 2; ++d1)
+    for (int d2 = 0; d2 < 2; ++d2) {
+      const int c1 = v1[d1] / n0, c2 = v2[d2] / n0;
+      const int l1 = v1[d1] - c1 * n0, l2 = v2[d2] - c2 * n0;
+      const bool in = l1 >= lo && l1 < hi && l2 >= lo && l2 < hi;
+      a[d1][d2] = in ? cells[(size_t)c1 * L + c2] : bg;
+    }
+  const double w0 = (a[1][0] + a[1][1]) / 2.0, w0m = (a[0][0] + a[0][1]) / 2.0;
+  const double w1 = (a[0][1] + a[1][1]) / 2.0, w1m = (a[0][0] + a[1][0]) / 2.0;
+  w64[idx] = w0;
+  w64[n2 + idx] = w1;
+  f[idx] = h * (w0 - w0m);
+  f[n2 + idx] = h * (w1 - w1m);
+}
+
 constexpr int kTX = 64;  // i3 extent of a tile (one wavefront)
 constexpr int kTY = 4;   // i2 extent of a tile (four wavefronts)
 
@@ -90,6 +117,7 @@ struct Cells {
   const TC* a;
   int L, n0, lo, hi;
   TC bg;
+  int dim;
 };
 
 // 2.5D tiled stencil on the cell values.  The edge weights are not read from
@@ -246,10 +274,79 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u, Cells
                            (blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * zc)));
 }
 
+// d = 2: the 5-point stencil on the cell values, one thread per node (the
+// neighbours come from L2; the field is N^2, at most 4M nodes), weights as
+// in k_assemble2d (bit for bit in double).  blockIdx.y = system.
+template <typename TU, typename TC, typename TO, typename C, int MODE, bool INCL>
+__global__ __launch_bounds__(256) void k_stencil2d(const TU* __restrict__ u, Cells<TC> cc,
+                                                   const double* __restrict__ f, TO* __restrict__ out,
+                                                   double* __restrict__ partial, const Scalars* __restrict__ s,
+                                                   int gate, int N, Batch bt) {
+  const int b = blockIdx.y;
+  if (s && !gate_open(s[b], gate)) return;
+  u += b * bt.vs;
+  out += b * bt.vs;
+  if (MODE == 1) f += b * bt.vs;
+  const TC* __restrict__ cells = cc.a + (size_t)(b / bt.per) * bt.ws;
+  const size_t n2 = (size_t)N * N;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double dot = 0.0;
+  if (idx < n2) {
+    const int p2 = (int)(idx % N), p1 = (int)(idx / N);
+    const int p1m = p1 == 0 ? N - 1 : p1 - 1, p1p = p1 + 1 == N ? 0 : p1 + 1;
+    const int p2m = p2 == 0 ? N - 1 : p2 - 1, p2p = p2 + 1 == N ? 0 : p2 + 1;
+    const int n0 = cc.n0;
+    const int v1[2] = {p1m, p1}, v2[2] = {p2m, p2};
+    C a[2][2];
+#pragma unroll
+    for (int d1 = 0; d1 < 2; ++d1)
+#pragma unroll
+      for (int d2 = 0; d2 < 2; ++d2) {
+        const int c1 = v1[d1] / n0, c2 = v2[d2] / n0;
+        C v = (C)cells[(size_t)c1 * cc.L + c2];
+        if constexpr (INCL) {
+          const int l1 = v1[d1] - c1 * n0, l2 = v2[d2] - c2 * n0;
+          if (!(l1 >= cc.lo && l1 < cc.hi && l2 >= cc.lo && l2 < cc.hi)) v = (C)cc.bg;
+        }
+        a[d1][d2] = v;
+      }
+    const C hf = (C)0.5;
+    const C w0c = (a[1][0] + a[1][1]) * hf, w0m = (a[0][0] + a[0][1]) * hf;
+    const C w1c = (a[0][1] + a[1][1]) * hf, w1m = (a[0][0] + a[1][0]) * hf;
+    const C uc = (C)u[idx];
+    C ku = w0c * (uc - (C)u[(size_t)p1p * N + p2]) + w0m * (uc - (C)u[(size_t)p1m * N + p2]);
+    ku += w1c * (uc - (C)u[(size_t)p1 * N + p2p]) + w1m * (uc - (C)u[(size_t)p1 * N + p2m]);
+    if (MODE == 0) {
+      const TO o = (TO)ku;
+      out[idx] = o;
+      dot = (double)uc * (double)o;
+    } else {
+      const double res = f[idx] - (double)ku;
+      out[idx] = (TO)res;
+      dot = res * res;
+    }
+  }
+  block_sum_store(dot, partial + (size_t)b * gridDim.x + blockIdx.x);
+}
+
 template <typename TU, typename TC, typename TO, typename C, int MODE>
 int run_stencil(kp_context* ctx, const TU* u, Cells<TC> cc, const double* f, TO* out,
                 double* partial, int* nparts, const Scalars* s, int gate, int N, const Batch& bt) {
   ScopedTimer tm(ctx, MODE == 1 ? KP_TIMER_RESIDUAL : KP_TIMER_STENCIL);
+  if (cc.dim == 2) {
+    const int g2 = (int)(((size_t)N * N + 255) / 256);
+    if (g2 > kMaxPartials || bt.nsys > 65535) return fail(KP_ERR_ARG, "stencil: 2D grid of N=%d too large", N);
+    const dim3 grid(g2, bt.nsys);
+    if (cc.lo > 0 || cc.hi < cc.n0)
+      hipLaunchKernelGGL((k_stencil2d<TU, TC, TO, C, MODE, true>), grid, dim3(256), 0, ctx->stream, u, cc, f,
+                         out, partial, s, gate, N, bt);
+    else
+      hipLaunchKernelGGL((k_stencil2d<TU, TC, TO, C, MODE, false>), grid, dim3(256), 0, ctx->stream, u, cc,
+                         f, out, partial, s, gate, N, bt);
+    KP_HIP(hipGetLastError());
+    *nparts = g2;
+    return KP_OK;
+  }
   const int gx = (N + kTX - 1) / kTX;
   const int gy = (N + kTY - 1) / kTY;
   // Enough planes per block to amortize the register queue, enough blocks to fill 256 CUs.
@@ -298,6 +395,14 @@ int launch_assemble(kp_context* ctx, kp_coeff* c) {
   const size_t n3 = (size_t)c->N * c->N * c->N;
   const int blocks = (int)((n3 + 255) / 256);
   const CellGeom cg = geom_of(c);
+  if (c->dim == 2) {
+    const size_t n2 = (size_t)c->N * c->N;
+    hipLaunchKernelGGL(k_assemble2d, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, ctx->stream, c->cells,
+                       c->L, c->n0, cg.lo, cg.hi, cg.bg, c->N, 1.0 / c->N, c->w64, c->f);
+    KP_HIP(hipGetLastError());
+    if (c->cells32) return launch_cast_f64_f32(ctx, c->cells, c->cells32, (size_t)c->L * c->L);
+    return KP_OK;
+  }
   hipLaunchKernelGGL(k_assemble, dim3(blocks), dim3(256), 0, ctx->stream, c->cells, c->L, c->n0, cg.lo,
                      cg.hi, cg.bg, c->N, 1.0 / c->N, c->w64, c->f);
   KP_HIP(hipGetLastError());
@@ -312,7 +417,7 @@ int stencil_parts_max(int N) {
 
 template <typename TC>
 Cells<TC> cells_of(const TC* a, const CellGeom& cg) {
-  return Cells<TC>{a, cg.L, cg.n0, cg.lo, cg.hi, (TC)cg.bg};
+  return Cells<TC>{a, cg.L, cg.n0, cg.lo, cg.hi, (TC)cg.bg, cg.dim};
 }
 
 int launch_stencil_f64(kp_context* ctx, const double* p, const double* cells, const CellGeom& cg,

@@ -64,3 +64,20 @@ def test_lowrank_factors_errors():
     info = kp._lib.PrecondInfo()
     assert lib.kp_lowrank_factors(16, 1e-3, 4, buf, 4, C.byref(info)) == KP_ERR_ARG
     assert b"capacity" in lib.kp_last_error()
+
+
+@pytest.mark.parametrize("N", [16, 64, 320, 512])
+def test_lowrank_factors_2d_match_oracle(N):
+    """The library's 2D factors (host C++: Jacobi for small N, subspace iteration
+    above) against the oracle's numpy eigen-truncation: same rank, the same
+    G_R to 1e-12 relative, the same rho range and truncation error."""
+    import paper_2007_06524_amd as kp
+    from oracle import twod as td
+    F, info = kp.lowrank_factors_2d(N, 1e-3)
+    Fo, io = td.lowrank_factors_2d(N, 1e-3)
+    assert info["rank"] == io["R"]
+    G = np.einsum("ki,kj->ij", F[0], F[1])
+    Go = np.einsum("ki,kj->ij", Fo[0], Fo[1])
+    assert np.abs(G - Go).max() <= 1e-12 * np.abs(Go).max()
+    assert abs(info["rho_min"] - io["rho_min"]) < 1e-9 and abs(info["rho_max"] - io["rho_max"]) < 1e-9
+    assert abs(info["cp_rel_err"] - io["rel_err"]) < 1e-9

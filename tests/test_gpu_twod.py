@@ -1,0 +1,174 @@
+"""GPU parity of the 2D problem (d = 2; Table 2) against the 2D oracle, through
+the C ABI.
+
+Tolerances as in the 3D tests: assembly 1e-15 relative; stencil FP64 1e-13,
+FP32 4e-6 relative to max |w| max |p|; preconditioner FP64 1e-12, BF16 1e-2,
+FP16 2e-3 (norm-wise); solves to a true relative residual 1e-8 by the oracle's
+operator; a_hom (2 x 2) within 1e-6 relative of the oracle's.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2007_06524_amd as kp  # noqa: E402
+from oracle import twod as td  # noqa: E402
+from workloads import even_factors, random_field  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = kp.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def cells2(L, lo, hi, seed, binary=False):
+    g = np.random.default_rng(np.random.SeedSequence((seed, 2)))
+    if binary:
+        return np.where(g.random((L, L)) < 0.5, hi, lo)
+    return lo + (hi - lo) * g.random((L, L))
+
+
+@pytest.mark.parametrize("L,n0,k,bg", [(4, 4, None, None), (7, 3, None, None), (33, 4, None, None),
+                                       (8, 4, 2, 0.4), (5, 6, 4, 2.0)])
+def test_2d_assembly_and_stencil_parity(ctx, L, n0, k, bg):
+    cells = cells2(L, 1.0, 10.0, seed=L * n0)
+    N = L * n0
+    co = kp.Coeff(ctx, cells, n0, "fp64", inclusion=k, background=bg)
+    assert co.dim == 2 and co.N == N
+    w, f = co.fields()
+    wr = td.edge_weights_2d(cells, n0, k, bg)
+    np.testing.assert_allclose(host(w), wr, rtol=1e-15, atol=0)
+    fr = np.stack([td.corrector_rhs_2d(wr, i) for i in (1, 2)])
+    np.testing.assert_allclose(host(f), fr, rtol=0, atol=1e-15 * np.abs(wr).max() / N)
+    p = random_field(N, seed=N, dims=2)
+    ref = td.stiffness_apply_2d(wr, p)
+    scale = np.abs(wr).max() * np.abs(p).max()
+    assert np.abs(host(kp.stiffness_apply(ctx, co, dev(p))) - ref).max() <= 1e-13 * scale
+    co.free()
+    cm = kp.Coeff(ctx, cells, n0, "mixed_bf16", inclusion=k, background=bg)
+    assert np.abs(host(kp.stiffness_apply(ctx, cm, dev(p), precision="mixed_bf16")) - ref).max() <= 4e-6 * scale
+    cm.free()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed_bf16", 1e-2), ("mixed_fp16", 2e-3)])
+@pytest.mark.parametrize("N,R", [(16, 3), (72, 4), (256, 5)])
+def test_2d_precond_apply(ctx, prec, tol, N, R):
+    """Random even factors: sum_k C1^k X (C2^k)^T against the oracle's dense
+    circulants, under every tile configuration at N = 256 (the kernels that build
+    the circulant operand in LDS and the wave-streamed ones)."""
+    F = even_factors(N, R, seed=N + R)[:2]
+    pc = kp.Precond(ctx, N, precision=prec, factors=F, dim=2)
+    x = random_field(N, seed=3, dims=2)
+    ref = td.circulant_2d_apply(F, x)
+    z = host(pc.apply(dev(x)))
+    assert np.linalg.norm(z - ref) <= tol * np.linalg.norm(ref)
+    if N == 256:
+        ncfg = 2 * (4 if prec == "fp64" else 12)
+        table = pc.autotune(reps=1)
+        assert {t[0] for t in table} == {1, 2}               # no stage (i) in 2D
+        for c in range(ncfg):
+            pc.tiles = (0, c, c)
+            z = host(pc.apply(dev(x)))
+            assert np.linalg.norm(z - ref) <= tol * np.linalg.norm(ref), c
+    pc.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16"])
+@pytest.mark.parametrize("L,n0,k,bg,binary", [(16, 4, None, None, False), (12, 4, 2, 0.4, True)])
+def test_2d_solve_against_oracle(ctx, prec, L, n0, k, bg, binary):
+    cells = cells2(L, 0.4 if binary else 1.0, 1.0 if binary else 10.0, seed=L + n0, binary=binary)
+    N = L * n0
+    co = kp.Coeff(ctx, cells, n0, prec, inclusion=k, background=bg)
+    pc = kp.Precond(ctx, N, 1e-3, 0, prec, dim=2)
+    ref = td.solve_correctors_2d(cells, n0, tol=1e-12, k=k, background=bg)
+    phis = []
+    for i in (1, 2):
+        x, st, status = kp.solve(ctx, co, pc, rhs=i, tol=1e-8)
+        assert status == kp.KP_OK, st
+        xh = host(x)
+        f = ref["fs"][i - 1]
+        assert np.linalg.norm(f - td.stiffness_apply_2d(ref["w"], xh)) <= 1e-8 * np.linalg.norm(f)
+        assert np.linalg.norm(xh - ref["phis"][i - 1]) <= 1e-6 * np.linalg.norm(ref["phis"][i - 1])
+        phis.append(x)
+    A = kp.homogenized_matrix(ctx, co, phis)
+    assert A.shape == (2, 2)
+    assert np.abs(A - ref["ahom"]).max() <= 1e-6 * np.abs(ref["ahom"]).max()
+    # the library's a_hom formula on the oracle's own solutions
+    Ao = kp.homogenized_matrix(ctx, co, [dev(p) for p in ref["phis"]])
+    vox = td.voxel_field_2d(cells, n0, k, bg)
+    np.testing.assert_allclose(Ao, td.homogenized_matrix_2d(vox, ref["phis"], ref["fs"]), atol=1e-13)
+    co.free()
+    pc.free()
+
+
+def test_2d_checkerboard_keller_dykhne_gpu(ctx):
+    """The regular two-phase checkerboard at n0 = 32 (N = 64): the GPU a_hom equals
+    the oracle's and lies within 5 % of sqrt(alpha beta), a_11 = a_22, a_12 = 0."""
+    cells = np.array([[1.0, 4.0], [4.0, 1.0]])
+    co = kp.Coeff(ctx, cells, 32, "fp64")
+    pc = kp.Precond(ctx, 64, 1e-3, 0, "fp64", dim=2)
+    phis = [kp.solve(ctx, co, pc, rhs=i, tol=1e-10)[0] for i in (1, 2)]
+    A = kp.homogenized_matrix(ctx, co, phis)
+    ref = td.solve_correctors_2d(cells, 32, tol=1e-12)["ahom"]
+    assert np.abs(A - ref).max() <= 1e-7 * np.abs(ref).max()
+    assert abs(A[0, 0] - A[1, 1]) < 1e-7 and abs(A[0, 1]) < 1e-7 and abs(A[0, 0] - 2.0) < 0.05 * 2.0
+    co.free()
+    pc.free()
+
+
+def test_2d_largest_paper_size(ctx):
+    """L = 512, n0 = 4 (N = 2048, 4.2M unknowns), alpha = 1/4 binary {0.4, 1}, the
+    largest 2D case of Table 2: mixed solves to 1e-8 by the oracle's operator,
+    a_hom within the harmonic / arithmetic bounds of the voxel field."""
+    cells = cells2(512, 0.4, 1.0, seed=512, binary=True)
+    co = kp.Coeff(ctx, cells, 4, "mixed_bf16", inclusion=2, background=0.4)
+    pc = kp.Precond(ctx, 2048, 1e-3, 0, "mixed_bf16", dim=2)
+    pc.autotune(reps=1)
+    w = td.edge_weights_2d(cells, 4, 2, 0.4)
+    phis = []
+    for i in (1, 2):
+        x, st, status = kp.solve(ctx, co, pc, rhs=i, tol=1e-8)
+        assert status == kp.KP_OK, st
+        f = td.corrector_rhs_2d(w, i)
+        assert np.linalg.norm(f - td.stiffness_apply_2d(w, host(x))) <= 1e-8 * np.linalg.norm(f)
+        phis.append(x)
+    A = kp.homogenized_matrix(ctx, co, phis)
+    vox = td.voxel_field_2d(cells, 4, 2, 0.4)
+    for i in range(2):
+        assert 1.0 / np.mean(1.0 / vox) <= A[i, i] <= vox.mean()
+    assert abs(A[0, 1] - A[1, 0]) <= 1e-6 * A[0, 0]
+    co.free()
+    pc.free()
+
+
+def test_2d_errors(ctx):
+    cells = cells2(4, 1.0, 2.0, seed=1)
+    co = kp.Coeff(ctx, cells, 4, "fp64")
+    pc3 = kp.Precond(ctx, 16, 1e-3, 0, "fp64")
+    pc2 = kp.Precond(ctx, 16, 1e-3, 0, "fp64", dim=2)
+    with pytest.raises(kp.KronPCGError) as e:
+        kp.solve(ctx, co, pc3, rhs=1)                     # 2D coefficient, 3D preconditioner
+    assert e.value.status == -6
+    with pytest.raises(kp.KronPCGError) as e:
+        kp.solve(ctx, co, pc2, rhs=3)                     # no third corrector in 2D
+    assert e.value.status == -1
+    with pytest.raises(kp.KronPCGError) as e:
+        kp.solve_batched(ctx, [co], [pc2])
+    assert e.value.status == -6
+    for o in (co, pc3, pc2):
+        o.free()
