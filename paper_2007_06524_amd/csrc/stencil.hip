@@ -329,6 +329,157 @@ __global__ __launch_bounds__(256) void k_stencil2d(const TU* __restrict__ u, Cel
   block_sum_store(dot, partial + (size_t)b * gridDim.x + blockIdx.x);
 }
 
+// Row-segment variant for N a multiple of 256 and n0 = 4 (the paper's cell
+// size and the benchmark's): a block of 256 threads owns a 256-wide segment of
+// i3 and kRY = 8 consecutive i2 rows (two cells) and marches along i1 over TZ
+// planes; every thread carries one i3 position of all eight rows (register
+// queues along i1 as above).  The in-row neighbours of plane z come from a
+// double-buffered LDS copy of the block's rows (one barrier per plane); only
+// the two segment-edge threads read a neighbour from global memory (N > 256),
+// and the only halo rows are the two i2 neighbours of the row group, so the
+// field is read about (1 + 2/8 + 1/TZ) times, against the 64 x 4 tile's i2 and
+// i3 halos (whose single-float column reads fetch whole lines of other tiles).
+// With n0 = 4 the eight rows touch three cell rows, so a layer of cell values
+// is 3 x 2 registers and a row's voxel rows map to them statically.  Weights
+// as in k_stencil (bit for bit in double).
+constexpr int kRY = 8;
+
+template <typename TU, typename TC, typename TO, typename C, int MODE, bool INCL>
+__global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, Cells<TC> cc,
+                                                      const double* __restrict__ f,
+                                                      TO* __restrict__ out, double* __restrict__ partial,
+                                                      const Scalars* __restrict__ s, int gate, int N,
+                                                      int TZ, int gz, Batch bt) {
+  constexpr int N0 = 4;
+  const int b = blockIdx.z / gz, zc = blockIdx.z - b * gz;
+  if (s && !gate_open(s[b], gate)) return;
+  u += b * bt.vs;
+  out += b * bt.vs;
+  if (MODE == 1) f += b * bt.vs;
+  const TC* __restrict__ cells = cc.a + (size_t)(b / bt.per) * bt.ws;
+  const int L = cc.L;
+  __shared__ TU su[2][kRY][256];
+  const int tx = threadIdx.x;
+  const int i3 = blockIdx.x * 256 + tx;
+  const int r0 = blockIdx.y * kRY;  // first i2 row of the group (a multiple of 8: cell row r0 / 4)
+  const int z0 = zc * TZ, z1 = min(z0 + TZ, N);
+  const size_t NN = (size_t)N * N;
+  const int i3m = i3 == 0 ? N - 1 : i3 - 1, i3p = i3 + 1 == N ? 0 : i3 + 1;
+  const int rm = r0 == 0 ? N - 1 : r0 - 1, rp = r0 + kRY == N ? 0 : r0 + kRY;  // halo rows
+  // Cell rows of the group: slot 0 = the cell row above (voxel row r0 - 1), 1 and 2 its own.
+  const int cr = r0 / N0;
+  const int c2L[3] = {(cr == 0 ? L - 1 : cr - 1) * L, cr * L, (cr + 1) * L};
+  const int c3[2] = {i3m / N0, i3 / N0};
+  const int l3[2] = {i3m - c3[0] * N0, i3 - c3[1] * N0};
+  bool in3[2] = {true, true};
+  if constexpr (INCL) {
+    in3[0] = l3[0] >= cc.lo && l3[0] < cc.hi;
+    in3[1] = l3[1] >= cc.lo && l3[1] < cc.hi;
+  }
+  auto layer = [&](int c1, C (&a)[3][2]) {
+    const size_t base = (size_t)c1 * L * L;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int d3 = 0; d3 < 2; ++d3) a[k][d3] = (C)cells[base + c2L[k] + c3[d3]];
+  };
+  C um[kRY], uc[kRY], un[kRY];
+  C a0[3][2], a1[3][2];
+  int cz = z0 / N0, rz = z0 - cz * N0;
+  {
+    const int zm = z0 == 0 ? N - 1 : z0 - 1;
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) {
+      um[r] = (C)u[zm * NN + (size_t)(r0 + r) * N + i3];
+      uc[r] = (C)u[z0 * NN + (size_t)(r0 + r) * N + i3];
+    }
+    layer(zm / N0, a0);
+    layer(cz, a1);
+  }
+  double dot = 0.0;
+  int buf = 0;
+  for (int z = z0; z < z1; ++z) {
+    const size_t base = (size_t)z * NN;
+    const int zp = z + 1 >= N ? 0 : z + 1;
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) {
+      un[r] = (C)u[zp * NN + (size_t)(r0 + r) * N + i3];
+      su[buf][r][tx] = (TU)uc[r];
+    }
+    const C hm = (C)u[base + (size_t)rm * N + i3], hp = (C)u[base + (size_t)rp * N + i3];
+    __syncthreads();
+    const C q = (C)0.25;
+    const int rzm = rz == 0 ? N0 - 1 : rz - 1;
+    const bool in0 = !INCL || (rzm >= cc.lo && rzm < cc.hi), in1 = !INCL || (rz >= cc.lo && rz < cc.hi);
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) {
+      const C u2m = r > 0 ? uc[r - 1] : hm;
+      const C u2p = r + 1 < kRY ? uc[r + 1] : hp;
+      const C u3m = tx > 0 ? (C)su[buf][r][tx - 1]
+                           : (N == 256 ? (C)su[buf][r][255] : (C)u[base + (size_t)(r0 + r) * N + i3m]);
+      const C u3p = tx < 255 ? (C)su[buf][r][tx + 1]
+                             : (N == 256 ? (C)su[buf][r][0] : (C)u[base + (size_t)(r0 + r) * N + i3p]);
+      C e0[2][2], e1[2][2];
+#pragma unroll
+      for (int d2 = 0; d2 < 2; ++d2) {
+        const int vr = r - 1 + d2;                           // voxel row r0 + vr
+        const int k = vr < 0 ? 0 : 1 + vr / N0;              // its cell slot
+        const int l2 = vr < 0 ? N0 - 1 : vr % N0;            // its row inside the cell
+#pragma unroll
+        for (int d3 = 0; d3 < 2; ++d3) {
+          if constexpr (INCL) {
+            const bool t = l2 >= cc.lo && l2 < cc.hi && in3[d3];
+            e0[d2][d3] = (in0 && t) ? a0[k][d3] : (C)cc.bg;
+            e1[d2][d3] = (in1 && t) ? a1[k][d3] : (C)cc.bg;
+          } else {
+            e0[d2][d3] = a0[k][d3];
+            e1[d2][d3] = a1[k][d3];
+          }
+        }
+      }
+      const C w0c = (((e1[1][1] + e1[0][1]) + e1[1][0]) + e1[0][0]) * q;
+      const C w0m = (((e0[1][1] + e0[0][1]) + e0[1][0]) + e0[0][0]) * q;
+      const C w1c = (((e1[1][1] + e0[1][1]) + e1[1][0]) + e0[1][0]) * q;
+      const C w1m = (((e1[0][1] + e0[0][1]) + e1[0][0]) + e0[0][0]) * q;
+      const C w2c = (((e1[1][1] + e0[1][1]) + e1[0][1]) + e0[0][1]) * q;
+      const C w2m = (((e1[1][0] + e0[1][0]) + e1[0][0]) + e0[0][0]) * q;
+      const C c = uc[r];
+      C ku = w0c * (c - un[r]) + w0m * (c - um[r]);
+      ku += w1c * (c - u2p) + w1m * (c - u2m);
+      ku += w2c * (c - u3p) + w2m * (c - u3m);
+      const size_t idx = base + (size_t)(r0 + r) * N + i3;
+      if (MODE == 0) {
+        const TO o = (TO)ku;
+        out[idx] = o;
+        dot += (double)c * (double)o;
+      } else {
+        const double res = f[idx] - (double)ku;
+        out[idx] = (TO)res;
+        dot += res * res;
+      }
+    }
+    // next plane: layer a1 becomes a0; a new layer when z + 1 starts a cell
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int d3 = 0; d3 < 2; ++d3) a0[k][d3] = a1[k][d3];
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) {
+      um[r] = uc[r];
+      uc[r] = un[r];
+    }
+    if (++rz == N0) {
+      rz = 0;
+      ++cz;
+      if (z + 1 < z1) layer(cz, a1);
+    }
+    buf ^= 1;  // the other LDS buffer next plane: one barrier per plane suffices
+  }
+  const size_t nparts = (size_t)gridDim.x * gridDim.y * gz;
+  block_sum_store(dot, partial + b * nparts +
+                           (blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * zc)));
+}
+
 template <typename TU, typename TC, typename TO, typename C, int MODE>
 int run_stencil(kp_context* ctx, const TU* u, Cells<TC> cc, const double* f, TO* out,
                 double* partial, int* nparts, const Scalars* s, int gate, int N, const Batch& bt) {
@@ -346,6 +497,25 @@ int run_stencil(kp_context* ctx, const TU* u, Cells<TC> cc, const double* f, TO*
     KP_HIP(hipGetLastError());
     *nparts = g2;
     return KP_OK;
+  }
+  if (N % 256 == 0 && cc.n0 == 4) {
+    // Row-segment kernel: enough blocks to fill 256 CUs with 8-plane chunks.
+    int TZ = 32;
+    const size_t rows = (size_t)(N / 256) * (N / kRY);
+    while (TZ > 8 && rows * ((N + TZ - 1) / TZ) * bt.nsys < 1024) TZ /= 2;
+    const int gz = (N + TZ - 1) / TZ;
+    if (rows * gz <= (size_t)kMaxPartials && (size_t)gz * bt.nsys <= 65535) {
+      const dim3 grid(N / 256, N / kRY, gz * bt.nsys);
+      if (cc.lo > 0 || cc.hi < cc.n0)
+        hipLaunchKernelGGL((k_stencil_rows<TU, TC, TO, C, MODE, true>), grid, dim3(256), 0, ctx->stream, u,
+                           cc, f, out, partial, s, gate, N, TZ, gz, bt);
+      else
+        hipLaunchKernelGGL((k_stencil_rows<TU, TC, TO, C, MODE, false>), grid, dim3(256), 0, ctx->stream, u,
+                           cc, f, out, partial, s, gate, N, TZ, gz, bt);
+      KP_HIP(hipGetLastError());
+      *nparts = (int)(rows * gz);
+      return KP_OK;
+    }
   }
   const int gx = (N + kTX - 1) / kTX;
   const int gy = (N + kTY - 1) / kTY;

@@ -163,3 +163,23 @@ def test_batched_c4_full_size(ctx):
         assert np.abs(A[m] - A[m].T).max() <= 1e-6 * np.abs(A[m]).max()
         assert all(harm <= A[m][i, i] <= arith for i in range(3))
     free(coeffs, owned)
+
+
+def test_batched_n256_row_kernel(ctx):
+    """Two realizations at L = 64 (N = 256, the row-segment stencil kernel with a
+    batch of six systems): each system's a_hom as its single solve's."""
+    from workloads import cells_bernoulli
+    cos, cells = [], []
+    for j in range(2):
+        c = cells_bernoulli(64, 1.0, 10.0, 0.5, seed=700 + j)
+        cells.append(c)
+        cos.append(kp.Coeff(ctx, c, 4, "mixed_bf16"))
+    pc = kp.Precond(ctx, 256, 1e-3, 5, "mixed_bf16")
+    xs, stats, A, status = kp.solve_batched(ctx, cos, [pc, pc], tol=1e-8)
+    assert status == kp.KP_OK and all(s["relres_true"] <= 1e-8 for s in stats)
+    for j in range(2):
+        single = [kp.solve(ctx, cos[j], pc, rhs=i, tol=1e-8)[0] for i in (1, 2, 3)]
+        As = kp.homogenized_matrix(ctx, cos[j], single)
+        assert np.abs(A[j] - As).max() <= 1e-6 * np.abs(As).max()
+    for o in cos + [pc]:
+        o.free()

@@ -23,6 +23,8 @@ from workloads import cells_bernoulli, cells_uniform, random_field  # noqa: E402
 # (Fig. Emp_a12_M20), a continuous law on a larger sub-cell, and odd ranges.
 CASES = [(3, 4, 2, 0.4, "binary"), (4, 4, 2, 0.4, "binary"), (2, 6, 4, 2.0, "uniform"),
          (5, 8, 2, 0.4, "binary"), (3, 5, 3, 1.5, "uniform")]
+# N = 256 with n0 = 4: the row-segment stencil kernel
+BIG = [(64, 4, 2, 0.4, "binary")]
 
 
 @pytest.fixture(scope="module")
@@ -63,7 +65,7 @@ def test_inclusion_assembly_parity(ctx, L, n0, k, bg, law):
     co.free()
 
 
-@pytest.mark.parametrize("L,n0,k,bg,law", CASES)
+@pytest.mark.parametrize("L,n0,k,bg,law", CASES + BIG)
 def test_inclusion_stencil_parity(ctx, L, n0, k, bg, law):
     """FP64 and FP32 stencils (weights rebuilt from the cells with the sub-cell
     masks) against the oracle's operator; the FP64 apply also equals the stencil

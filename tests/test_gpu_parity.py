@@ -59,7 +59,7 @@ def test_assembly_parity(ctx, L, n0):
 
 
 # ------------------------------------------------------------------ stencil
-@pytest.mark.parametrize("L,n0", [(4, 4), (5, 3), (12, 4), (18, 4), (65, 2)])
+@pytest.mark.parametrize("L,n0", [(4, 4), (5, 3), (12, 4), (18, 4), (65, 2), (64, 4)])
 def test_stencil_fp64_parity(ctx, L, n0):
     cells = cells_lognormal(L, 1.0, seed=2000 + L)
     N = L * n0
@@ -73,7 +73,7 @@ def test_stencil_fp64_parity(ctx, L, n0):
     co.free()
 
 
-@pytest.mark.parametrize("L,n0", [(4, 4), (12, 4), (65, 2)])
+@pytest.mark.parametrize("L,n0", [(4, 4), (12, 4), (65, 2), (64, 4)])
 def test_stencil_fp32_parity(ctx, L, n0):
     cells = cells_uniform(L, 1.0, 100.0, seed=3000 + L)
     N = L * n0
