@@ -1137,6 +1137,26 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
                                false, nsys);
   const bool f16 = pc->precision == KP_MIXED_FP16;
   const int ntile = sixteen ? kTiles16 : kTiles64, ncfg = 2 * ntile;
+  // 16-bit: stage (iii) is timed with the fused dot products it carries in the
+  // solvers (scratch r, q of zeros and a partials buffer), so the choice
+  // includes the cost of its epilogue.
+  void *dr = nullptr, *dq = nullptr, *dpart = nullptr;
+  const size_t dcap = (size_t)5 * nsys * 65536;
+  struct Scratch {
+    kp_context* ctx;
+    void** p[3];
+    ~Scratch() {
+      for (void** q : p)
+        if (*q) dev_free(ctx, *q);
+    }
+  } scratch{ctx, {&dr, &dq, &dpart}};
+  if (sixteen) {
+    KP_TRY(dev_alloc(ctx, &dr, nsys * n3 * sizeof(float)));
+    KP_TRY(dev_alloc(ctx, &dq, nsys * n3 * sizeof(float)));
+    KP_TRY(dev_alloc(ctx, &dpart, dcap * sizeof(double)));
+    KP_HIP(hipMemsetAsync(dr, 0, nsys * n3 * sizeof(float), ctx->stream));
+    KP_HIP(hipMemsetAsync(dq, 0, nsys * n3 * sizeof(float), ctx->stream));
+  }
   int n = 0;
   for (int stg = pc->dim == 2 ? 1 : 0; stg < 3; ++stg) {
     const GemmArgs& g = stg == 0 ? st.s1 : (stg == 1 ? st.s2 : st.s3);
@@ -1144,11 +1164,20 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
     double best = 1e300;
     int best_cfg = -1;
     for (int c = 0; c < ncfg; ++c) {
+      GemmArgs gd = g;
+      if (sixteen && stg == 2) {
+        gd.vec = vec_ok(gd);
+        if ((size_t)5 * nsys * blocks16(gd, batch, c) <= dcap) {
+          gd.dr = (const float*)dr;
+          gd.dq = (const float*)dq;
+          gd.dpart = (double*)dpart;
+        }
+      }
       auto run = [&]() -> int {
         if (!sixteen) return run_gemm_f64(ctx, g, batch, c, stg);
         if (stg == 0) return run_gemm_16<0, bf16_t>(ctx, g, batch, f16, c);
         if (stg == 1) return run_gemm_16<1, bf16_t>(ctx, g, batch, f16, c);
-        return run_gemm_16<2, float>(ctx, g, batch, f16, c);
+        return run_gemm_16<2, float>(ctx, gd, batch, f16, c);
       };
       KP_TRY(run());
       KP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
