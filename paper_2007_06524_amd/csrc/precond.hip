@@ -830,7 +830,8 @@ constexpr int kCfg64[kTiles64][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}}
 constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 0},  {128, 64, 64, 0},   {64, 128, 64, 0},
                                      {128, 128, 64, 0}, {128, 128, 32, 0},  {64, 128, 32, 0},
                                      {64, 128, 64, 1},  {128, 128, 64, 1},  {128, 128, 32, 1},
-                                     {32, 64, 32, 1},   {128, 128, 8, 2},   {256, 64, 8, 2}};
+                                     {32, 64, 32, 1},   {128, 128, 8, 2},   {256, 64, 8, 2},
+                                     {128, 128, 128, 1}, {64, 128, 128, 1}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
@@ -932,6 +933,7 @@ int resolve16(const GemmArgs& g, int batch, int cfg, int* order) {
   *order = cfg / kTiles16;
   int t = cfg % kTiles16;
   if (!tile_ok(g, t) && kCfg16[t][3] == 2) t = 7;
+  if (!tile_ok(g, t) && t >= 12) t = t == 12 ? 7 : 6;
   if (!tile_ok(g, t)) t = t == 9 ? 0 : (t == 8 ? 4 : (t == 7 ? 3 : 2));
   return t;
 }
@@ -961,7 +963,9 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
     case 8: launch16<STAGE, 128, 128, 32, 1, TO>(ctx, g, batch, f16); break;
     case 9: launch16<STAGE, 32, 64, 32, 1, TO>(ctx, g, batch, f16); break;
     case 10: launch16<STAGE, 128, 128, 8, 2, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 256, 64, 8, 2, TO>(ctx, g, batch, f16); break;
+    case 11: launch16<STAGE, 256, 64, 8, 2, TO>(ctx, g, batch, f16); break;
+    case 12: launch16<STAGE, 128, 128, 128, 1, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 64, 128, 128, 1, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
