@@ -35,7 +35,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "c3_mixed_bf16_n256_kernels.md"
 # first template argument).
 TRAFFIC_PATTERNS = {
     "mixed_bf16": {"gemm_mode3": r"k_gemm_16c?<0,", "gemm_mode2": r"k_gemm_16c?<1,",
-                   "gemm_mode1": r"k_gemm_16c?<2,", "stencil": r"k_stencil<float, float, float, float, 0>"},
+                   "gemm_mode1": r"k_gemm_16c?<2,", "stencil": r"k_stencil(_rows)?<float, float, float, float, 0,"},
     "mixed_fp16": {},
     "fp64": {},
 }
