@@ -1109,7 +1109,10 @@ int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, fl
 
 // Times every tile configuration of every stage (`reps` launches each, after
 // one warm-up launch) for a batch of nsys systems and keeps the fastest per
-// stage in tiles[].  Scratch: T, U (nsys R N^3 elements each), X (nsys N^3
+// stage in tiles[].  The stages are tuned in order and every timed launch of
+// stage s > first follows an untimed launch of stage s - 1 with its chosen
+// tiles, as in an apply: the candidate then finds its input operand where the
+// previous stage left it in the caches.  Scratch: T, U (nsys R N^3 elements each), X (nsys N^3
 // inputs), Z (nsys N^3 outputs); all NULL: the context workspace (nsys = 1).
 // T, U and X are zero-filled first.
 int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_tile_timing* table,
@@ -1161,10 +1164,31 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
     KP_HIP(hipMemsetAsync(dr, 0, nsys * n3 * sizeof(float), ctx->stream));
     KP_HIP(hipMemsetAsync(dq, 0, nsys * n3 * sizeof(float), ctx->stream));
   }
+  struct Events {
+    std::vector<hipEvent_t> ev;
+    ~Events() {
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+  } evs;
+  evs.ev.reserve(2 * (size_t)reps);
+  for (int r = 0; r < 2 * reps; ++r) {
+    hipEvent_t e;
+    KP_HIP(hipEventCreate(&e));
+    evs.ev.push_back(e);
+  }
+  const int first = pc->dim == 2 ? 1 : 0;
   int n = 0;
-  for (int stg = pc->dim == 2 ? 1 : 0; stg < 3; ++stg) {
+  for (int stg = first; stg < 3; ++stg) {
     const GemmArgs& g = stg == 0 ? st.s1 : (stg == 1 ? st.s2 : st.s3);
     const int batch = stg == 1 ? nsys * pc->R : nsys;
+    auto run_prev = [&]() -> int {
+      if (stg == first) return KP_OK;
+      const GemmArgs& gp = stg == 1 ? st.s1 : st.s2;
+      const int bp = stg == 2 ? nsys * pc->R : nsys;
+      if (!sixteen) return run_gemm_f64(ctx, gp, bp, tiles[stg - 1], stg - 1);
+      if (stg == 1) return run_gemm_16<0, bf16_t>(ctx, gp, bp, f16, tiles[0]);
+      return run_gemm_16<1, bf16_t>(ctx, gp, bp, f16, tiles[1]);
+    };
     double best = 1e300;
     int best_cfg = -1;
     for (int c = 0; c < ncfg; ++c) {
@@ -1183,14 +1207,22 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         if (stg == 1) return run_gemm_16<1, bf16_t>(ctx, g, batch, f16, c);
         return run_gemm_16<2, float>(ctx, gd, batch, f16, c);
       };
+      KP_TRY(run_prev());
       KP_TRY(run());
-      KP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-      for (int r = 0; r < reps; ++r) KP_TRY(run());
-      KP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
-      KP_HIP(hipEventSynchronize(ctx->ev1));
-      float ms = 0.f;
-      KP_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-      const double avg = (double)ms / reps;
+      for (int r = 0; r < reps; ++r) {
+        KP_TRY(run_prev());
+        KP_HIP(hipEventRecord(evs.ev[2 * r], ctx->stream));
+        KP_TRY(run());
+        KP_HIP(hipEventRecord(evs.ev[2 * r + 1], ctx->stream));
+      }
+      KP_HIP(hipEventSynchronize(evs.ev[2 * reps - 1]));
+      double tot = 0.0;
+      for (int r = 0; r < reps; ++r) {
+        float ms = 0.f;
+        KP_HIP(hipEventElapsedTime(&ms, evs.ev[2 * r], evs.ev[2 * r + 1]));
+        tot += ms;
+      }
+      const double avg = tot / reps;
       if (table && n < cap) {
         kp_tile_timing& e = table[n];
         e.stage = stg;

@@ -351,7 +351,16 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
                                                       const Scalars* __restrict__ s, int gate, int N,
                                                       int TZ, int gz, Batch bt) {
   constexpr int N0 = 4;
-  const int b = blockIdx.z / gz, zc = blockIdx.z - b * gz;
+  // XCD-aware block order: consecutive hardware blocks go to the eight XCDs in
+  // turn, so hardware block h takes logical block (h mod 8) * (nb / 8) + h / 8
+  // (nb a multiple of 8): each XCD then works through a contiguous run of row
+  // groups and plane chunks, and the halo rows and planes that neighbouring
+  // blocks share are fetched once into that XCD's L2.
+  const unsigned gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+  unsigned lb = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((nb & 7u) == 0) lb = (lb & 7u) * (nb >> 3) + (lb >> 3);
+  const int bx = (int)(lb % gx), by = (int)((lb / gx) % gy), bz = (int)(lb / (gx * gy));
+  const int b = bz / gz, zc = bz - b * gz;
   if (s && !gate_open(s[b], gate)) return;
   u += b * bt.vs;
   out += b * bt.vs;
@@ -360,8 +369,8 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
   const int L = cc.L;
   __shared__ TU su[2][kRY][256];
   const int tx = threadIdx.x;
-  const int i3 = blockIdx.x * 256 + tx;
-  const int r0 = blockIdx.y * kRY;  // first i2 row of the group (a multiple of 8: cell row r0 / 4)
+  const int i3 = bx * 256 + tx;
+  const int r0 = by * kRY;  // first i2 row of the group (a multiple of 8: cell row r0 / 4)
   const int z0 = zc * TZ, z1 = min(z0 + TZ, N);
   const size_t NN = (size_t)N * N;
   const int i3m = i3 == 0 ? N - 1 : i3 - 1, i3p = i3 + 1 == N ? 0 : i3 + 1;
@@ -476,8 +485,7 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
     buf ^= 1;  // the other LDS buffer next plane: one barrier per plane suffices
   }
   const size_t nparts = (size_t)gridDim.x * gridDim.y * gz;
-  block_sum_store(dot, partial + b * nparts +
-                           (blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * zc)));
+  block_sum_store(dot, partial + b * nparts + (bx + (size_t)gx * (by + (size_t)gy * zc)));
 }
 
 template <typename TU, typename TC, typename TO, typename C, int MODE>
