@@ -831,17 +831,18 @@ constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 0},  {128, 64, 64, 0},   {64, 
                                      {128, 128, 64, 0}, {128, 128, 32, 0},  {64, 128, 32, 0},
                                      {64, 128, 64, 1},  {128, 128, 64, 1},  {128, 128, 32, 1},
                                      {32, 64, 32, 1},   {128, 128, 8, 2},   {256, 64, 8, 2},
-                                     {128, 128, 128, 1}, {64, 128, 128, 1}};
+                                     {128, 128, 128, 1}, {64, 128, 128, 1}, {256, 64, 64, 1},
+                                     {256, 64, 128, 1}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
 }
 
-// Large problems: 128 x 128 x 64 with the circulant operand in LDS (else the
-// same tile streamed) in the XCD-grouped order, the fastest on the N = 256
-// stages when measured; small ones: 64 x 64.
+// Large problems: 256 x 64 x 128 with the circulant operand in LDS (else
+// 128 x 128 x 64, else that tile streamed) in the XCD-grouped order, the
+// fastest on the N = 256 stages when measured; small ones: 64 x 64.
 int heuristic16(const GemmArgs& g, int batch) {
-  if ((long long)g.M * g.Nn * batch >= 128LL * 128 * 256) return 7 + kTiles16;
+  if ((long long)g.M * g.Nn * batch >= 128LL * 128 * 256) return 15 + kTiles16;
   return 0;
 }
 
@@ -933,7 +934,7 @@ int resolve16(const GemmArgs& g, int batch, int cfg, int* order) {
   *order = cfg / kTiles16;
   int t = cfg % kTiles16;
   if (!tile_ok(g, t) && kCfg16[t][3] == 2) t = 7;
-  if (!tile_ok(g, t) && t >= 12) t = t == 12 ? 7 : 6;
+  if (!tile_ok(g, t) && t >= 12) t = t == 13 ? 6 : 7;
   if (!tile_ok(g, t)) t = t == 9 ? 0 : (t == 8 ? 4 : (t == 7 ? 3 : 2));
   return t;
 }
@@ -965,7 +966,9 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
     case 10: launch16<STAGE, 128, 128, 8, 2, TO>(ctx, g, batch, f16); break;
     case 11: launch16<STAGE, 256, 64, 8, 2, TO>(ctx, g, batch, f16); break;
     case 12: launch16<STAGE, 128, 128, 128, 1, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 64, 128, 128, 1, TO>(ctx, g, batch, f16); break;
+    case 13: launch16<STAGE, 64, 128, 128, 1, TO>(ctx, g, batch, f16); break;
+    case 14: launch16<STAGE, 256, 64, 64, 1, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 256, 64, 128, 1, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;
