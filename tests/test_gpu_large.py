@@ -83,9 +83,10 @@ def test_wave_kernels_n512(ctx):
     pts = [tuple(int(v) for v in g.integers(0, N, 3)) for _ in range(6)] + [(0, 0, 0), (N - 1, N - 1, N - 1)]
     ref = sampled_apply(F, x, pts)
     xd = torch.from_numpy(x).cuda()
+    ntile = 16                                       # 16-bit tile shapes (cfg = tile + ntile * order)
     for t in (7, 10, 11):
         for order in (0, 1):
-            c = t + 12 * order
+            c = t + ntile * order
             pc.tiles = (c, c, c)
             z = pc.apply(xd)
             got = np.array([float(z[p]) for p in pts])
@@ -98,13 +99,15 @@ def ahom_bounds_ok(A, cells):
     return all(harm <= A[i, i] <= arith for i in range(3))
 
 
-def test_c3_full_size_mixed(ctx):
-    """64^3-cell Bernoulli{1,100} checkerboard, N = 256, mixed BF16 with the tiles the
-    autotuner picks (the benchmark's launch configuration)."""
+@pytest.mark.parametrize("prec", ["mixed_fp16", "mixed_bf16"])
+def test_c3_full_size_mixed(ctx, prec):
+    """64^3-cell Bernoulli{1,100} checkerboard, N = 256, mixed FP16 (the benchmark's
+    precision) and BF16 with the tiles the autotuner picks (the benchmark's launch
+    configuration)."""
     cells = config_cells("c3")
     N = 256
-    co = kp.Coeff(ctx, cells, 4, "mixed_bf16")
-    pc = kp.Precond(ctx, N, 1e-3, 5, "mixed_bf16")
+    co = kp.Coeff(ctx, cells, 4, prec)
+    pc = kp.Precond(ctx, N, 1e-3, 5, prec)
     pc.autotune(reps=1)
     check_sampled_apply(pc, N, 5, seed=256)
     # solves: oracle residual, a_hom against the plain FP64 GPU solve
