@@ -220,7 +220,7 @@ constexpr int kRedBlocks = 1024;
 constexpr int kMaxPartials = 65536;
 // Number of GEMM tile configurations (double and 16-bit kernels).
 constexpr int kTiles64 = 4;
-constexpr int kTiles16 = 16;
+constexpr int kTiles16 = 18;
 
 // Times every tile configuration for a batch of nsys systems on scratch T, U,
 // X, Z (NULL: the context workspace, nsys = 1) and stores the fastest in tiles[3].

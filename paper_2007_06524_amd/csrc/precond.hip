@@ -832,7 +832,7 @@ constexpr int kCfg16[kTiles16][4] = {{64, 64, 64, 0},  {128, 64, 64, 0},   {64, 
                                      {64, 128, 64, 1},  {128, 128, 64, 1},  {128, 128, 32, 1},
                                      {32, 64, 32, 1},   {128, 128, 8, 2},   {256, 64, 8, 2},
                                      {128, 128, 128, 1}, {64, 128, 128, 1}, {256, 64, 64, 1},
-                                     {256, 64, 128, 1}};
+                                     {256, 64, 128, 1},  {96, 64, 32, 1},   {96, 128, 32, 1}};
 
 int heuristic64(const GemmArgs& g) {
   return (long long)g.M * g.Nn >= 256LL * 128 * 128 ? 3 : 0;
@@ -968,7 +968,9 @@ int run_gemm_16(kp_context* ctx, GemmArgs g, int batch, bool f16, int cfg) {
     case 12: launch16<STAGE, 128, 128, 128, 1, TO>(ctx, g, batch, f16); break;
     case 13: launch16<STAGE, 64, 128, 128, 1, TO>(ctx, g, batch, f16); break;
     case 14: launch16<STAGE, 256, 64, 64, 1, TO>(ctx, g, batch, f16); break;
-    default: launch16<STAGE, 256, 64, 128, 1, TO>(ctx, g, batch, f16); break;
+    case 15: launch16<STAGE, 256, 64, 128, 1, TO>(ctx, g, batch, f16); break;
+    case 16: launch16<STAGE, 96, 64, 32, 1, TO>(ctx, g, batch, f16); break;
+    default: launch16<STAGE, 96, 128, 32, 1, TO>(ctx, g, batch, f16); break;
   }
   KP_HIP(hipGetLastError());
   return KP_OK;

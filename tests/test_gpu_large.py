@@ -83,7 +83,7 @@ def test_wave_kernels_n512(ctx):
     pts = [tuple(int(v) for v in g.integers(0, N, 3)) for _ in range(6)] + [(0, 0, 0), (N - 1, N - 1, N - 1)]
     ref = sampled_apply(F, x, pts)
     xd = torch.from_numpy(x).cuda()
-    ntile = 16                                       # 16-bit tile shapes (cfg = tile + ntile * order)
+    ntile = 18                                       # 16-bit tile shapes (cfg = tile + ntile * order)
     for t in (7, 10, 11):
         for order in (0, 1):
             c = t + ntile * order

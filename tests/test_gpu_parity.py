@@ -293,23 +293,24 @@ def test_coeff_update_and_timing(ctx):
     co.free()
 
 
-@pytest.mark.parametrize("N", [72, 128, 256])
+@pytest.mark.parametrize("N", [72, 96, 128, 256])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed_bf16", 1e-2), ("mixed_fp16", 2e-3)])
 def test_every_tile_configuration_matches(ctx, prec, tol, N):
     """The autotuner's candidates all compute the same operator: tune, then check the
     apply with every configuration, on a ragged size (N = 72, R = 3: edge tiles, K not
-    a multiple of the K tile), on N = 128 (interior tiles: the kernels that build the
-    circulant operand in LDS) and on N = 256 (also the wave-streamed kernels, whose
-    last stage switches between three circulants along K)."""
+    a multiple of the K tile), on N = 96 (the circulant-in-LDS kernels with 32-row and
+    96-row tiles, three 16-row fragments per wave), on N = 128 (interior tiles) and on
+    N = 256 (also the wave-streamed kernels, whose last stage switches between three
+    circulants along K)."""
     F = even_factors(N, 3, seed=N)
     pc = kp.Precond(ctx, N, precision=prec, factors=F)
-    ncfg = 2 * (4 if prec == "fp64" else 16)     # tile shapes x two block orders
+    ncfg = 2 * (4 if prec == "fp64" else 18)     # tile shapes x two block orders
     table = pc.autotune(reps=1)
     assert len(table) == 3 * ncfg and all(t[6] > 0 for t in table)
     assert {t[4] for t in table} == {0, 1}
     if prec != "fp64":
         kinds = {t[5] for t in table}           # 0 streamed, 1 circulant in LDS, 2 wave-streamed
-        assert kinds == ({0} if N == 72 else ({0, 1} if N == 128 else {0, 1, 2})), kinds
+        assert kinds == ({0} if N == 72 else ({0, 1} if N in (96, 128) else {0, 1, 2})), kinds
     tuned = pc.tiles
     assert all(0 <= t < ncfg for t in tuned)
     x = random_field(N, seed=8)

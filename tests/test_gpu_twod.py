@@ -78,7 +78,7 @@ def test_2d_precond_apply(ctx, prec, tol, N, R):
     z = host(pc.apply(dev(x)))
     assert np.linalg.norm(z - ref) <= tol * np.linalg.norm(ref)
     if N == 256:
-        ncfg = 2 * (4 if prec == "fp64" else 16)
+        ncfg = 2 * (4 if prec == "fp64" else 18)
         table = pc.autotune(reps=1)
         assert {t[0] for t in table} == {1, 2}               # no stage (i) in 2D
         for c in range(ncfg):
