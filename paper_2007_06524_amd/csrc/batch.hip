@@ -297,13 +297,17 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
     }
   }
 
-  // Tiles for each group's batch size, tuned once per preconditioner and size.
+  // Tiles for each group, tuned once per preconditioner on a batch of about
+  // 2^24 unknowns (every stage then has blocks enough to fill the chip; at most
+  // the group's systems, a prefix of its buffers), so that the cost of tuning
+  // does not grow with the batch and chunks of different sizes share one result.
   for (Group& g : B.groups) {
-    if (g.pc->tuned_nsys == g.nsys) continue;
+    const int nt = (int)std::min<size_t>((size_t)g.nsys, std::max<size_t>(1, ((size_t)1 << 24) / g.n3));
+    if (g.pc->tuned_nsys == nt) continue;
     kp_precond* pcm = const_cast<kp_precond*>(g.pc);  // the tile cache only
-    KP_TRY(autotune_precond(ctx, pcm, g.nsys, 2, nullptr, 0, nullptr, pcm->tile_batch, g.T, g.U,
+    KP_TRY(autotune_precond(ctx, pcm, nt, 2, nullptr, 0, nullptr, pcm->tile_batch, g.T, g.U,
                             mixed ? (void*)g.x16 : g.r, g.z));
-    pcm->tuned_nsys = g.nsys;
+    pcm->tuned_nsys = nt;
   }
 
   KP_HIP(hipEventRecord(ctx->ev0, ctx->stream));

@@ -144,12 +144,14 @@ def test_batched_edge_cases(ctx):
     free(coeffs, owned, [pc_other, cm, pm])
 
 
-def test_batched_c4_full_size(ctx):
+@pytest.mark.parametrize("prec", ["mixed_fp16", "mixed_bf16"])
+def test_batched_c4_full_size(ctx, prec):
     """96 log-normal realizations, L cycling over {8, 12, 16, 24} (N = 32 .. 96), mixed
-    BF16: every system converges; sampled systems against the oracle; a_hom of every
-    realization symmetric and inside the harmonic / arithmetic bounds."""
+    FP16 (the benchmark's) and BF16: every system converges; sampled systems against
+    the oracle; a_hom of every realization symmetric and inside the harmonic /
+    arithmetic bounds."""
     cells_list = batched_realizations(96, sizes=(8, 12, 16, 24), sigma=1.0, seed=4)
-    coeffs, pcs, owned = make_batch(ctx, cells_list, 4, "mixed_bf16")
+    coeffs, pcs, owned = make_batch(ctx, cells_list, 4, prec)
     xs, stats, A, status = kp.solve_batched(ctx, coeffs, pcs, tol=1e-8)
     assert status == kp.KP_OK
     assert all(s["status"] == kp.KP_OK and s["relres_true"] <= 1e-8 for s in stats)

@@ -28,7 +28,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16", "mixed_fp16"])
 def test_mc_parity_with_oracle(ctx, prec):
     """alpha = 1/4 sub-cells, binary {0.4, 1}: L = 3 (N = 12), M = 10 in chunks of 4
     (the last chunk partial, the coefficient objects re-assembled in place)."""
@@ -72,14 +72,14 @@ def test_mc_chunking_invariance(ctx):
 
 def test_mc_decay_rate_paper_setting(ctx):
     """eq. var in the setting of Fig. Emp_a12_M20 (3D, n0 = 4, alpha = 1/4,
-    lambda = 0.4): with M = 64 realizations at L = 2, 4, 8, 16 (mixed BF16), the
+    lambda = 0.4): with M = 64 realizations at L = 2, 4, 8, 16 (mixed FP16), the
     fitted slope of log sigma_L^M(a_11) against log L lies within 0.5 of -3/2,
     and a_hom stays between the harmonic and arithmetic means of the voxel field."""
     cfg = MC_FIGURE
     sig = []
     for L in (2, 4, 8, 16):
         cells = mc_realizations(L, 64, cfg["lo"], cfg["hi"], cfg["p"], seed=cfg["seed"])
-        pc = kp.Precond(ctx, L * cfg["n0"], 1e-3, 0, "mixed_bf16")
+        pc = kp.Precond(ctx, L * cfg["n0"], 1e-3, 0, "mixed_fp16")
         A, mean, sd, st, status = kp.mc_homogenize(ctx, cells, cfg["n0"], pc, inclusion=cfg["incl"],
                                                    background=cfg["background"])
         assert status == kp.KP_OK and st["max_relres_true"] <= 1e-8
@@ -106,7 +106,8 @@ def test_mc_argument_errors(ctx):
     pc.free()
 
 
-def test_fast_convergence_reliable_update(ctx):
+@pytest.mark.parametrize("prec", ["mixed_bf16", "mixed_fp16"])
+def test_fast_convergence_reliable_update(ctx, prec):
     """Regression: every cell perturbed at L = 2 (a periodic array of identical
     sub-cell inclusions) converges in about a dozen iterations, so the float
     recursion reaches its accuracy floor before the fixed replacement period;
@@ -114,8 +115,8 @@ def test_fast_convergence_reliable_update(ctx):
     batched mixed solves reach 1e-8 by the oracle's operator)."""
     from oracle import assembly as asm
     cells = np.ones((2, 2, 2))
-    co = kp.Coeff(ctx, cells, 4, "mixed_bf16", inclusion=2, background=0.4)
-    pc = kp.Precond(ctx, 8, 1e-3, 0, "mixed_bf16")
+    co = kp.Coeff(ctx, cells, 4, prec, inclusion=2, background=0.4)
+    pc = kp.Precond(ctx, 8, 1e-3, 0, prec)
     w = asm.edge_weights(cells, 4, 2, 0.4)
     for i in (1, 2, 3):
         x, st, status = kp.solve(ctx, co, pc, rhs=i, tol=1e-8)

@@ -88,7 +88,7 @@ def test_2d_precond_apply(ctx, prec, tol, N, R):
     pc.free()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16", "mixed_fp16"])
 @pytest.mark.parametrize("L,n0,k,bg,binary", [(16, 4, None, None, False), (12, 4, 2, 0.4, True)])
 def test_2d_solve_against_oracle(ctx, prec, L, n0, k, bg, binary):
     cells = cells2(L, 0.4 if binary else 1.0, 1.0 if binary else 10.0, seed=L + n0, binary=binary)
@@ -131,13 +131,15 @@ def test_2d_checkerboard_keller_dykhne_gpu(ctx):
     pc.free()
 
 
-def test_2d_largest_paper_size(ctx):
+@pytest.mark.parametrize("prec", ["mixed_fp16", "mixed_bf16"])
+def test_2d_largest_paper_size(ctx, prec):
     """L = 512, n0 = 4 (N = 2048, 4.2M unknowns), alpha = 1/4 binary {0.4, 1}, the
-    largest 2D case of Table 2: mixed solves to 1e-8 by the oracle's operator,
-    a_hom within the harmonic / arithmetic bounds of the voxel field."""
+    largest 2D case of Table 2: mixed solves (FP16, the benchmark's, and BF16) to
+    1e-8 by the oracle's operator, a_hom within the harmonic / arithmetic bounds of
+    the voxel field."""
     cells = cells2(512, 0.4, 1.0, seed=512, binary=True)
-    co = kp.Coeff(ctx, cells, 4, "mixed_bf16", inclusion=2, background=0.4)
-    pc = kp.Precond(ctx, 2048, 1e-3, 0, "mixed_bf16", dim=2)
+    co = kp.Coeff(ctx, cells, 4, prec, inclusion=2, background=0.4)
+    pc = kp.Precond(ctx, 2048, 1e-3, 0, prec, dim=2)
     pc.autotune(reps=1)
     w = td.edge_weights_2d(cells, 4, 2, 0.4)
     phis = []
