@@ -242,11 +242,13 @@ int kp_precond_from_factors(kp_context* ctx, int N, int R, const double* factors
  * 1: circulant operand built in LDS from the circulants' first columns, only
  * the data operand streamed; 2: as 1, the data operand streamed by each wave
  * straight into registers; a configuration whose kernel cannot run the stage
- * runs as the nearest one that can, and reports that one's kernel), average
- * ms}; *count the number of configurations timed.  Block order 0 walks the
- * column tiles of
- * the data operand fastest; order 1 gives all row tiles of one column tile to
- * blocks on the same XCD (one L2), so that column tile is read from HBM once.
+ * runs as the nearest one that can, and its entry reports the tile, order and
+ * kernel that ran), average ms}; *count the number of configurations timed.
+ * Block order 0 walks the column tiles of the data operand fastest; order 1
+ * gives all row tiles of one column tile to blocks on the same XCD (one L2),
+ * so that column tile is read from HBM once.  Each timed launch follows an
+ * untimed launch of the previous stage with its chosen tiles, after the
+ * intermediates have been overwritten (cache state as in a solve).
  * Synchronizes the stream. */
 typedef struct {
   int stage, bm, bn, bk, order, circ;

@@ -1117,7 +1117,11 @@ int launch_precond_16(kp_context* ctx, const kp_precond* pc, const bf16_t* x, fl
 // stage in tiles[].  The stages are tuned in order and every timed launch of
 // stage s > first follows an untimed launch of stage s - 1 with its chosen
 // tiles, as in an apply: the candidate then finds its input operand where the
-// previous stage left it in the caches.  Scratch: T, U (nsys R N^3 elements each), X (nsys N^3
+// previous stage left it in the caches.  Before that, the intermediates T and
+// U (2 R N^3 values, more than the 256 MB last-level cache at N = 256) are
+// overwritten with zeros, so that the rest of the candidate's operands are no
+// warmer than in a solve, where about a gigabyte of vector traffic separates
+// two applies (the values do not matter: the scratch is zero-filled).  Scratch: T, U (nsys R N^3 elements each), X (nsys N^3
 // inputs), Z (nsys N^3 outputs); all NULL: the context workspace (nsys = 1).
 // T, U and X are zero-filled first.
 int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_tile_timing* table,
@@ -1212,9 +1216,12 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         if (stg == 1) return run_gemm_16<1, bf16_t>(ctx, g, batch, f16, c);
         return run_gemm_16<2, float>(ctx, gd, batch, f16, c);
       };
+      const size_t inter = nsys * n3 * pc->R * el;
       KP_TRY(run_prev());
       KP_TRY(run());
       for (int r = 0; r < reps; ++r) {
+        KP_HIP(hipMemsetAsync(T, 0, inter, ctx->stream));
+        if (pc->dim == 3) KP_HIP(hipMemsetAsync(U, 0, inter, ctx->stream));
         KP_TRY(run_prev());
         KP_HIP(hipEventRecord(evs.ev[2 * r], ctx->stream));
         KP_TRY(run());
@@ -1231,13 +1238,15 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
       if (table && n < cap) {
         kp_tile_timing& e = table[n];
         e.stage = stg;
-        const int t = c % ntile;
+        // the tile that ran: a configuration whose kernel cannot run this
+        // product falls back to another (resolve16)
+        int ord = c / ntile;
+        const int t = sixteen ? resolve16(g, batch, c, &ord) : c % ntile;
         e.bm = sixteen ? kCfg16[t][0] : kCfg64[t][0];
         e.bn = sixteen ? kCfg16[t][1] : kCfg64[t][1];
         e.bk = sixteen ? kCfg16[t][2] : 16;
-        int ord;
-        e.circ = sixteen ? kCfg16[resolve16(g, batch, c, &ord)][3] : 0;
-        e.order = c / ntile;
+        e.circ = sixteen ? kCfg16[t][3] : 0;
+        e.order = ord;
         e.ms = avg;
       }
       ++n;
