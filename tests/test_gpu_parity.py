@@ -311,6 +311,10 @@ def test_every_tile_configuration_matches(ctx, prec, tol, N):
     if prec != "fp64":
         kinds = {t[5] for t in table}           # 0 streamed, 1 circulant in LDS, 2 wave-streamed
         assert kinds == ({0} if N == 72 else ({0, 1} if N in (96, 128) else {0, 1, 2})), kinds
+        # entries name the tile that ran: 96-row tiles only where 96 divides N,
+        # 256-row tiles only where 256 does
+        rows = {t[1] for t in table}
+        assert (96 in rows) == (N == 96) and (256 in rows) == (N == 256), rows
     tuned = pc.tiles
     assert all(0 <= t < ncfg for t in tuned)
     x = random_field(N, seed=8)
