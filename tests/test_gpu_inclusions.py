@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 import paper_2007_06524_amd as kp  # noqa: E402
 from oracle import assembly as asm  # noqa: E402
 from oracle.homogenize import solve_correctors  # noqa: E402
-from workloads import cells_bernoulli, cells_uniform, random_field  # noqa: E402
+from workloads import cells_bernoulli, cells_two_contrast, cells_uniform, random_field  # noqa: E402
 
 # (L, n0, incl, background, law): the paper's alpha = 1/4 binary {1, lambda = 0.4}
 # (Fig. Emp_a12_M20), a continuous law on a larger sub-cell, and odd ranges.
@@ -106,6 +106,35 @@ def test_inclusion_solve_against_oracle(ctx, prec, L, n0, k, bg, law):
     A = kp.homogenized_matrix(ctx, co, phis)
     assert np.abs(A - ref["ahom"]).max() <= 1e-6 * np.abs(ref["ahom"]).max(), (A, ref["ahom"])
     vox = asm.voxel_field(cells, n0, k, bg)
+    for i in range(3):
+        assert 1.0 / np.mean(1.0 / vox) <= A[i, i] <= vox.mean()
+    co.free()
+    pc.free()
+
+
+@pytest.mark.parametrize("layered", [False, True])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp16"])
+def test_two_contrast_solve_against_oracle(ctx, prec, layered):
+    """The two-contrast realizations of Section 2: alpha = 1/4 sub-cell inclusions
+    of lambda + 0.3 or lambda + 0.6 on the background lambda = 0.4, the contrast
+    drawn per inclusion or set by layers of two cells; solves against the
+    oracle's (residual by its operator, a_hom, the mean bounds)."""
+    L, n0, k, lam = 4, 4, 2, 0.4
+    cells = cells_two_contrast(L, lam, (0.3, 0.6), 0.5, seed=70 + int(layered), layered=layered)
+    N = L * n0
+    co = kp.Coeff(ctx, cells, n0, prec, inclusion=k, background=lam)
+    pc = kp.Precond(ctx, N, 1e-3, 0, prec)
+    ref = solve_correctors(cells, n0, tol=1e-12, k=k, background=lam)
+    phis = []
+    for i in (1, 2, 3):
+        x, st, status = kp.solve(ctx, co, pc, rhs=i, tol=1e-8)
+        assert status == kp.KP_OK, st
+        f = ref["fs"][i - 1]
+        assert np.linalg.norm(f - asm.stiffness_apply(ref["w"], host(x))) <= 1e-8 * np.linalg.norm(f)
+        phis.append(x)
+    A = kp.homogenized_matrix(ctx, co, phis)
+    assert np.abs(A - ref["ahom"]).max() <= 1e-6 * np.abs(ref["ahom"]).max(), (A, ref["ahom"])
+    vox = asm.voxel_field(cells, n0, k, lam)
     for i in range(3):
         assert 1.0 / np.mean(1.0 / vox) <= A[i, i] <= vox.mean()
     co.free()

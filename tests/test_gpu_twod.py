@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2007_06524_amd as kp  # noqa: E402
 from oracle import twod as td  # noqa: E402
-from workloads import even_factors, random_field  # noqa: E402
+from workloads import cells_two_contrast, even_factors, random_field  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -112,6 +112,31 @@ def test_2d_solve_against_oracle(ctx, prec, L, n0, k, bg, binary):
     Ao = kp.homogenized_matrix(ctx, co, [dev(p) for p in ref["phis"]])
     vox = td.voxel_field_2d(cells, n0, k, bg)
     np.testing.assert_allclose(Ao, td.homogenized_matrix_2d(vox, ref["phis"], ref["fs"]), atol=1e-13)
+    co.free()
+    pc.free()
+
+
+@pytest.mark.parametrize("layered", [False, True])
+def test_2d_two_contrast(ctx, layered):
+    """The 2D two-contrast realizations of Section 2 (L = 16 and 24, the sizes of
+    its examples; alpha = 1/4 inclusions of lambda + 0.3 or lambda + 0.6 on
+    lambda = 0.4, drawn or in layers of two cells), mixed FP16: solves against
+    the 2D oracle's."""
+    L, n0, lam = (24 if layered else 16), 4, 0.4
+    cells = cells_two_contrast(L, lam, (0.3, 0.6), 0.5, seed=80 + L, layered=layered, dims=2)
+    N = L * n0
+    co = kp.Coeff(ctx, cells, n0, "mixed_fp16", inclusion=2, background=lam)
+    pc = kp.Precond(ctx, N, 1e-3, 0, "mixed_fp16", dim=2)
+    ref = td.solve_correctors_2d(cells, n0, tol=1e-12, k=2, background=lam)
+    phis = []
+    for i in (1, 2):
+        x, st, status = kp.solve(ctx, co, pc, rhs=i, tol=1e-8)
+        assert status == kp.KP_OK, st
+        f = ref["fs"][i - 1]
+        assert np.linalg.norm(f - td.stiffness_apply_2d(ref["w"], host(x))) <= 1e-8 * np.linalg.norm(f)
+        phis.append(x)
+    A = kp.homogenized_matrix(ctx, co, phis)
+    assert np.abs(A - ref["ahom"]).max() <= 1e-6 * np.abs(ref["ahom"]).max()
     co.free()
     pc.free()
 

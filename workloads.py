@@ -61,6 +61,25 @@ def cells_lognormal(L: int, sigma: float, seed, mu: float = 0.0) -> np.ndarray:
     return np.exp(mu + sigma * g.standard_normal((L, L, L))).astype(np.float64)
 
 
+def cells_two_contrast(L: int, lam: float, betas, p: float, seed, layered: bool = False,
+                       layer: int = 2, dims: int = 3) -> np.ndarray:
+    """Realizations with two contrast parameters (Section 2): a cell holds an
+    inclusion with probability p, of value lam + beta; beta is betas[0] or
+    betas[1] with equal probability, or, layered, betas[0] on the cells whose
+    index along the first axis lies in an even block of `layer` cells and
+    betas[1] on the others.  Cells without an inclusion take lam, which with
+    sub-cell inclusions is the background."""
+    g = _rng(seed)
+    shape = (L,) * dims
+    occupied = g.random(shape) < p
+    if layered:
+        even = (np.arange(L) // layer) % 2 == 0
+        beta = np.broadcast_to(np.where(even, betas[0], betas[1]).reshape((L,) + (1,) * (dims - 1)), shape)
+    else:
+        beta = np.where(g.random(shape) < 0.5, betas[0], betas[1])
+    return np.where(occupied, lam + beta, lam).astype(np.float64)
+
+
 def random_field(N: int, seed, dims: int = 3) -> np.ndarray:
     """Standard-normal nodal field of shape (N,)*dims (test vectors)."""
     g = _rng(seed)
