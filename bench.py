@@ -92,12 +92,10 @@ def kernel_rooflines(timing, N, R, prec, L):
             if prec != "fp64":
                 # The same launch against HBM: its 16-bit input and output (the
                 # intermediates hold R N^3 values each), the float z and the float
-                # r (and q for BF16's flexible beta) the last stage's dot products
-                # read.  At N = 256, R = 5 stages (ii) and (iii) do 128 and 119
-                # (BF16: 116) flop per such byte, below the 16-bit ridge of
-                # 2.5 PFLOP/s / 8 TB/s = 312 flop/B.
-                dots = 8 if prec == "mixed_fp16" else 12
-                per = {"gemm_mode3": 2 + 2 * R, "gemm_mode2": 4 * R, "gemm_mode1": 2 * R + dots}[name]
+                # r, q the last stage's dot products read.  At N = 256, R = 5 stages
+                # (ii) and (iii) do 128 and 116 flop per such byte, below the 16-bit
+                # ridge of 2.5 PFLOP/s / 8 TB/s = 312 flop/B.
+                per = {"gemm_mode3": 2 + 2 * R, "gemm_mode2": 4 * R, "gemm_mode1": 2 * R + 12}[name]
                 nbytes = float(per) * n3
                 gbs = nbytes / (avg_ms * 1e-3) / 1e9
                 rec["hbm"] = {"algorithmic": nbytes, "achieved": gbs, "peak": HBM_PEAK_GBS,

@@ -87,7 +87,6 @@ int fin(kp_context* ctx, Group& g, int np, int nvals, int mode) {
 
 // z = M r, the preconditioner dot products and p = (z - mz) + beta p.
 int precondition_and_update(kp_context* ctx, BatchState& B, Group& g, int fin_mode, bool have_q) {
-  have_q = have_q && B.mixed && !B.fp16;  // <q, z> only for the flexible beta (mixed BF16)
   int np = 0;
   if (B.mixed) {
     const PrecDots dots{(const float*)g.r, have_q ? (const float*)g.q : nullptr, g.part, g.part_cap};
@@ -337,8 +336,7 @@ extern "C" int pcg_solve_batched(kp_context* ctx, int n_inst, const kp_coeff* co
     for (Scalars& e : h) {
       std::memset(&e, 0, sizeof(Scalars));
       e.tol2ff = o.tol * o.tol;  // times ||f||^2 in FIN_FF
-      e.flexible = mixed && !B.fp16 ? 1 : 0;  // as the single solver
-      e.reliable = mixed ? 1 : 0;
+      e.flexible = mixed ? 1 : 0;
       e.x16_scale = e.x16_scale_next = 1.0;
       e.maxit = o.maxit;
       e.replace_every = o.replace_every;

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
       } else if (rr <= s->tol2ff) {
         s->done = 1;
         if (mode == FIN_RR_NOCOUNT) s->status = 1;  // a true residual: converged
-      } else if (mode == FIN_RR && s->reliable && rr <= kReliableDrop * s->rr_ref) {
+      } else if (mode == FIN_RR && s->flexible && rr <= kReliableDrop * s->rr_ref) {
         s->done = 1;  // the single solver's host loop takes the true residual and restarts
       }
       break;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
       }
       s->check = rr <= s->tol2ff || s->iters >= s->maxit ||
                  (s->replace_every > 0 && s->iters % s->replace_every == 0) ||
-                 (s->reliable && rr <= kReliableDrop * s->rr_ref);
+                 (s->flexible && rr <= kReliableDrop * s->rr_ref);
       if (s->check) s->rr_rec = rr;
       break;
     }

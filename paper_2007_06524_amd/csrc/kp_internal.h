@@ -48,8 +48,7 @@ struct Scalars {
   int done;       // 1: converged (recursive test) or broken down; kernels then no-op
   int breakdown;  // 1: <p,Kp> <= 0, rho <= 0 or non-finite
   int iters;      // iterations completed
-  int flexible;   // 1: Polak-Ribiere beta (needs <q, z>), 0: Fletcher-Reeves beta
-  int reliable;   // 1 (mixed precision): replace r once ||r|| falls 1e4 below the last true residual
+  int flexible;   // 1: Polak-Ribiere beta, 0: Fletcher-Reeves beta
   // Device-side control of the batched solver (FIN_RR_CTL / FIN_TRUE_CTL):
   int check;         // 1: take the true residual in this iteration
   int replaced;      // 1: r was replaced by the true residual in this iteration

@@ -6,12 +6,9 @@
 //
 // Plain FP64: standard PCG, beta = rho_new / rho.
 // Mixed: float vectors, float stencil on float cell values, BF16/FP16 MFMA
-// preconditioner; with BF16 flexible PCG (Polak-Ribiere beta, which tolerates
-// a preconditioner that is only approximately linear and symmetric because of
-// rounding), with FP16 (11 significant bits in the rounded residual and
-// intermediates) the standard beta, which converged in as many iterations and
-// spares the last GEMM stage the read of q for <q, z>; dot products, norms
-// and the zero-mean projection in double; x in
+// preconditioner, flexible PCG (Polak-Ribiere beta, which tolerates a
+// preconditioner that is only approximately linear and symmetric because of
+// rounding); dot products, norms and the zero-mean projection in double; x in
 // double, its increments accumulated in float and added into it before every
 // true residual;
 // every `replace_every` iterations the recursive residual is replaced by the
@@ -38,7 +35,6 @@ struct Solver {
   const kp_precond* pc;
   bool mixed;
   bool fp16;
-  bool flexible;     // Polak-Ribiere beta: mixed BF16
   int N;
   size_t n3;
   Scalars* s;        // device
@@ -82,7 +78,6 @@ int true_residual(Solver& S, bool into_r) {
 
 // z = M r; rho, mean(z), beta from the dot products; p = (z - mz) + beta p.
 int precondition_and_update(Solver& S, int fin_mode, bool have_q) {
-  have_q = have_q && S.flexible;  // <q, z> only for the flexible beta
   if (S.mixed) {
     // The last GEMM stage computes the dot products of z as it writes z.
     const PrecDots dots{(const float*)S.r, have_q ? (const float*)S.q : nullptr, S.part,
@@ -177,7 +172,6 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   S.pc = pc;
   S.mixed = mixed;
   S.fp16 = pc->precision == KP_MIXED_FP16;
-  S.flexible = pc->precision == KP_MIXED_BF16;
   S.N = c->N;
   S.n3 = unknowns(c->N, c->dim);
   const size_t vb = S.n3 * (mixed ? sizeof(float) : sizeof(double));
@@ -235,8 +229,7 @@ extern "C" int pcg_solve(kp_context* ctx, const kp_coeff* c, const kp_precond* p
   h = Scalars{};
   h.ff = ff;
   h.tol2ff = o.tol * o.tol * ff;
-  h.flexible = S.flexible ? 1 : 0;
-  h.reliable = mixed ? 1 : 0;
+  h.flexible = mixed ? 1 : 0;
   h.x16_scale = h.x16_scale_next = 1.0;
   KP_TRY(write_scalars(S, h));
   if (!o.use_x0) KP_TRY(launch_fill_f64(ctx, x_dev, 0.0, S.n3));

@@ -1154,10 +1154,8 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
   const bool f16 = pc->precision == KP_MIXED_FP16;
   const int ntile = sixteen ? kTiles16 : kTiles64, ncfg = 2 * ntile;
   // 16-bit: stage (iii) is timed with the fused dot products it carries in the
-  // solvers (scratch r of zeros, q too for BF16, whose flexible beta needs
-  // <q, z>, and a partials buffer), so the choice includes the cost of its
-  // epilogue.
-  const bool with_q = pc->precision == KP_MIXED_BF16;
+  // solvers (scratch r, q of zeros and a partials buffer), so the choice
+  // includes the cost of its epilogue.
   void *dr = nullptr, *dq = nullptr, *dpart = nullptr;
   const size_t dcap = (size_t)5 * nsys * 65536;
   struct Scratch {
@@ -1170,10 +1168,10 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
   } scratch{ctx, {&dr, &dq, &dpart}};
   if (sixteen) {
     KP_TRY(dev_alloc(ctx, &dr, nsys * n3 * sizeof(float)));
-    if (with_q) KP_TRY(dev_alloc(ctx, &dq, nsys * n3 * sizeof(float)));
+    KP_TRY(dev_alloc(ctx, &dq, nsys * n3 * sizeof(float)));
     KP_TRY(dev_alloc(ctx, &dpart, dcap * sizeof(double)));
     KP_HIP(hipMemsetAsync(dr, 0, nsys * n3 * sizeof(float), ctx->stream));
-    if (with_q) KP_HIP(hipMemsetAsync(dq, 0, nsys * n3 * sizeof(float), ctx->stream));
+    KP_HIP(hipMemsetAsync(dq, 0, nsys * n3 * sizeof(float), ctx->stream));
   }
   struct Events {
     std::vector<hipEvent_t> ev;
@@ -1208,7 +1206,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         gd.vec = vec_ok(gd);
         if ((size_t)5 * nsys * blocks16(gd, batch, c) <= dcap) {
           gd.dr = (const float*)dr;
-          gd.dq = (const float*)dq;  // NULL for FP16
+          gd.dq = (const float*)dq;
           gd.dpart = (double*)dpart;
         }
       }
