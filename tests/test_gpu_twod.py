@@ -161,7 +161,9 @@ def test_2d_largest_paper_size(ctx, prec):
     """L = 512, n0 = 4 (N = 2048, 4.2M unknowns), alpha = 1/4 binary {0.4, 1}, the
     largest 2D case of Table 2: mixed solves (FP16, the benchmark's, and BF16) to
     1e-8 by the oracle's operator, a_hom within the harmonic / arithmetic bounds of
-    the voxel field."""
+    the voxel field.  The flexible beta keeps them short (FP16 19 and 14
+    iterations, BF16 33 and 17); the standard beta took corrector 1 to 212 in
+    FP16, which the iteration bound catches."""
     cells = cells2(512, 0.4, 1.0, seed=512, binary=True)
     co = kp.Coeff(ctx, cells, 4, prec, inclusion=2, background=0.4)
     pc = kp.Precond(ctx, 2048, 1e-3, 0, prec, dim=2)
@@ -171,6 +173,7 @@ def test_2d_largest_paper_size(ctx, prec):
     for i in (1, 2):
         x, st, status = kp.solve(ctx, co, pc, rhs=i, tol=1e-8)
         assert status == kp.KP_OK, st
+        assert st["iters"] <= 60, st
         f = td.corrector_rhs_2d(w, i)
         assert np.linalg.norm(f - td.stiffness_apply_2d(w, host(x))) <= 1e-8 * np.linalg.norm(f)
         phis.append(x)
