@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte-Carlo statistics section")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D section")
     ap.add_argument("--mc-only", action="store_true", help="run only the Monte-Carlo statistics section")
+    ap.add_argument("--twod-only", action="store_true",
+                    help="run only the 2D section and print its JSON (a profiling aid)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched section (96 realizations of uneven L)")
     ap.add_argument("--batched-only", action="store_true",
@@ -309,9 +311,25 @@ def main():
     from paper_2007_06524_amd.profiling import kernel_source_digest, measured_traffic
     from workloads import CONFIGS, config_cells
 
+    if args.copy_probe_mib > 0:
+        # One elementwise kernel that reads and writes exactly copy_probe_mib MiB each:
+        # the reference for scaling the FETCH_SIZE / WRITE_SIZE counters.
+        src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.mc_only:
         ctx = kp.Context(0)
         out = montecarlo_section(kp, ctx, args.eps)
+        ctx.close()
+        print(json.dumps(out))
+        return
+
+    if args.twod_only:
+        ctx = kp.Context(0)
+        out = twod_section(kp, ctx, args.eps, reps=args.steps)
         ctx.close()
         print(json.dumps(out))
         return
@@ -322,15 +340,6 @@ def main():
         ctx.close()
         print(json.dumps(out))
         return
-
-    if args.copy_probe_mib > 0:
-        # One elementwise kernel that reads and writes exactly copy_probe_mib MiB each:
-        # the reference for scaling the FETCH_SIZE / WRITE_SIZE counters.
-        src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
 
     cfg = CONFIGS["c3"]
     n0, L = cfg["n0"], cfg["L"]
