@@ -331,18 +331,26 @@ __global__ __launch_bounds__(256) void k_stencil2d(const TU* __restrict__ u, Cel
 
 // Row-segment variant for N a multiple of 256 and n0 = 4 (the paper's cell
 // size and the benchmark's): a block of 256 threads owns a 256-wide segment of
-// i3 and kRY = 8 consecutive i2 rows (two cells) and marches along i1 over TZ
-// planes; every thread carries one i3 position of all eight rows (register
-// queues along i1 as above).  The in-row neighbours of plane z come from a
-// double-buffered LDS copy of the block's rows (one barrier per plane); only
-// the two segment-edge threads read a neighbour from global memory (N > 256),
-// and the only halo rows are the two i2 neighbours of the row group, so the
-// field is read about (1 + 2/8 + 1/TZ) times, against the 64 x 4 tile's i2 and
-// i3 halos (whose single-float column reads fetch whole lines of other tiles).
-// With n0 = 4 the eight rows touch three cell rows, so a layer of cell values
-// is 3 x 2 registers and a row's voxel rows map to them statically.  Weights
-// as in k_stencil (bit for bit in double).
+// i3 and RY consecutive i2 rows (8 for float fields, two cells; 4 for double
+// ones, one cell) and marches along i1 over TZ planes; every thread carries one
+// i3 position of all RY rows (register queues along i1 as above).  The in-row
+// neighbours of plane z come from a double-buffered LDS copy of the block's
+// rows (one barrier per plane); only the two segment-edge threads read a
+// neighbour from global memory (N > 256), and the only halo rows are the two
+// i2 neighbours of the row group, so the field is read about
+// (1 + 2/RY + 1/TZ) times, against the 64 x 4 tile's i2 and i3 halos (whose
+// single-float column reads fetch whole lines of other tiles).  With n0 = 4
+// the RY rows touch RY/4 + 1 cell rows, so a layer of cell values is
+// (RY/4 + 1) x 2 registers and a row's voxel rows map to them statically.
+// Weights as in k_stencil (bit for bit in double).
 constexpr int kRY = 8;
+
+// RY rows per thread: 8 for float fields, 4 for double ones (half the row
+// registers, so the double residual keeps more waves per SIMD).
+template <typename TU>
+constexpr int rows_per_thread() {
+  return sizeof(TU) == 8 ? 4 : kRY;
+}
 
 template <typename TU, typename TC, typename TO, typename C, int MODE, bool INCL>
 __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, Cells<TC> cc,
@@ -351,6 +359,8 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
                                                       const Scalars* __restrict__ s, int gate, int N,
                                                       int TZ, int gz, Batch bt) {
   constexpr int N0 = 4;
+  constexpr int RY = rows_per_thread<TU>();
+  constexpr int SL = RY / N0 + 1;  // cell rows a layer needs (the row above and RY / 4 own)
   // XCD-aware block order: consecutive hardware blocks go to the eight XCDs in
   // turn, so hardware block h takes logical block (h mod 8) * (nb / 8) + h / 8
   // (nb a multiple of 8): each XCD then works through a contiguous run of row
@@ -367,17 +377,20 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
   if (MODE == 1) f += b * bt.vs;
   const TC* __restrict__ cells = cc.a + (size_t)(b / bt.per) * bt.ws;
   const int L = cc.L;
-  __shared__ TU su[2][kRY][256];
+  __shared__ TU su[2][RY][256];
   const int tx = threadIdx.x;
   const int i3 = bx * 256 + tx;
-  const int r0 = by * kRY;  // first i2 row of the group (a multiple of 8: cell row r0 / 4)
+  const int r0 = by * RY;  // first i2 row of the group (a multiple of 4: cell row r0 / 4)
   const int z0 = zc * TZ, z1 = min(z0 + TZ, N);
   const size_t NN = (size_t)N * N;
   const int i3m = i3 == 0 ? N - 1 : i3 - 1, i3p = i3 + 1 == N ? 0 : i3 + 1;
-  const int rm = r0 == 0 ? N - 1 : r0 - 1, rp = r0 + kRY == N ? 0 : r0 + kRY;  // halo rows
-  // Cell rows of the group: slot 0 = the cell row above (voxel row r0 - 1), 1 and 2 its own.
+  const int rm = r0 == 0 ? N - 1 : r0 - 1, rp = r0 + RY == N ? 0 : r0 + RY;  // halo rows
+  // Cell rows of the group: slot 0 = the cell row above (voxel row r0 - 1), 1.. its own.
   const int cr = r0 / N0;
-  const int c2L[3] = {(cr == 0 ? L - 1 : cr - 1) * L, cr * L, (cr + 1) * L};
+  int c2L[SL];
+  c2L[0] = (cr == 0 ? L - 1 : cr - 1) * L;
+#pragma unroll
+  for (int k = 1; k < SL; ++k) c2L[k] = (cr + k - 1) * L;
   const int c3[2] = {i3m / N0, i3 / N0};
   const int l3[2] = {i3m - c3[0] * N0, i3 - c3[1] * N0};
   bool in3[2] = {true, true};
@@ -385,20 +398,20 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
     in3[0] = l3[0] >= cc.lo && l3[0] < cc.hi;
     in3[1] = l3[1] >= cc.lo && l3[1] < cc.hi;
   }
-  auto layer = [&](int c1, C (&a)[3][2]) {
+  auto layer = [&](int c1, C (&a)[SL][2]) {
     const size_t base = (size_t)c1 * L * L;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < SL; ++k)
 #pragma unroll
       for (int d3 = 0; d3 < 2; ++d3) a[k][d3] = (C)cells[base + c2L[k] + c3[d3]];
   };
-  C um[kRY], uc[kRY], un[kRY];
-  C a0[3][2], a1[3][2];
+  C um[RY], uc[RY], un[RY];
+  C a0[SL][2], a1[SL][2];
   int cz = z0 / N0, rz = z0 - cz * N0;
   {
     const int zm = z0 == 0 ? N - 1 : z0 - 1;
 #pragma unroll
-    for (int r = 0; r < kRY; ++r) {
+    for (int r = 0; r < RY; ++r) {
       um[r] = (C)u[zm * NN + (size_t)(r0 + r) * N + i3];
       uc[r] = (C)u[z0 * NN + (size_t)(r0 + r) * N + i3];
     }
@@ -411,7 +424,7 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
     const size_t base = (size_t)z * NN;
     const int zp = z + 1 >= N ? 0 : z + 1;
 #pragma unroll
-    for (int r = 0; r < kRY; ++r) {
+    for (int r = 0; r < RY; ++r) {
       un[r] = (C)u[zp * NN + (size_t)(r0 + r) * N + i3];
       su[buf][r][tx] = (TU)uc[r];
     }
@@ -421,9 +434,9 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
     const int rzm = rz == 0 ? N0 - 1 : rz - 1;
     const bool in0 = !INCL || (rzm >= cc.lo && rzm < cc.hi), in1 = !INCL || (rz >= cc.lo && rz < cc.hi);
 #pragma unroll
-    for (int r = 0; r < kRY; ++r) {
+    for (int r = 0; r < RY; ++r) {
       const C u2m = r > 0 ? uc[r - 1] : hm;
-      const C u2p = r + 1 < kRY ? uc[r + 1] : hp;
+      const C u2p = r + 1 < RY ? uc[r + 1] : hp;
       const C u3m = tx > 0 ? (C)su[buf][r][tx - 1]
                            : (N == 256 ? (C)su[buf][r][255] : (C)u[base + (size_t)(r0 + r) * N + i3m]);
       const C u3p = tx < 255 ? (C)su[buf][r][tx + 1]
@@ -469,11 +482,11 @@ __global__ __launch_bounds__(256) void k_stencil_rows(const TU* __restrict__ u, 
     }
     // next plane: layer a1 becomes a0; a new layer when z + 1 starts a cell
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < SL; ++k)
 #pragma unroll
       for (int d3 = 0; d3 < 2; ++d3) a0[k][d3] = a1[k][d3];
 #pragma unroll
-    for (int r = 0; r < kRY; ++r) {
+    for (int r = 0; r < RY; ++r) {
       um[r] = uc[r];
       uc[r] = un[r];
     }
@@ -508,12 +521,13 @@ int run_stencil(kp_context* ctx, const TU* u, Cells<TC> cc, const double* f, TO*
   }
   if (N % 256 == 0 && cc.n0 == 4) {
     // Row-segment kernel: enough blocks to fill 256 CUs with 8-plane chunks.
+    constexpr int RY = rows_per_thread<TU>();
     int TZ = 32;
-    const size_t rows = (size_t)(N / 256) * (N / kRY);
+    const size_t rows = (size_t)(N / 256) * (N / RY);
     while (TZ > 8 && rows * ((N + TZ - 1) / TZ) * bt.nsys < 1024) TZ /= 2;
     const int gz = (N + TZ - 1) / TZ;
     if (rows * gz <= (size_t)kMaxPartials && (size_t)gz * bt.nsys <= 65535) {
-      const dim3 grid(N / 256, N / kRY, gz * bt.nsys);
+      const dim3 grid(N / 256, N / RY, gz * bt.nsys);
       if (cc.lo > 0 || cc.hi < cc.n0)
         hipLaunchKernelGGL((k_stencil_rows<TU, TC, TO, C, MODE, true>), grid, dim3(256), 0, ctx->stream, u,
                            cc, f, out, partial, s, gate, N, TZ, gz, bt);
