@@ -503,9 +503,12 @@ __global__ __launch_bounds__(256) void k_gemm_16(GemmArgs g) {
 // (kp_precond::circ16), so the block loads those copies (2 planes x 8 x (N+8)
 // values, 8.4 KB at N = 256) once per circulant instead of streaming A tiles;
 // only the data operand B goes through the K loop.  All tiles must be interior
-// (checked by the launcher).  Dynamic LDS: the copies.
+// (checked by the launcher).  Dynamic LDS: the copies.  Launch bounds for three
+// blocks per CU: every tile fits in 168 registers without spilling (the
+// accumulators move from AGPRs to VGPRs), and the third block per CU took the
+// last stage at N = 256 from 110 to 101 us.
 template <int STAGE, int BM, int BN, int BK, bool F16, typename TO>
-__global__ __launch_bounds__(256) void k_gemm_16c(GemmArgs g) {
+__global__ __launch_bounds__(256, 3) void k_gemm_16c(GemmArgs g) {
   const int bz = blockIdx.z, bo = bz / g.bdiv, bi = bz - bo * g.bdiv;
   if (g.done && g.done[(long long)bo * g.done_stride]) return;
   static_assert(BK == 32 || BK == 64 || BK == 128, "K tile");
