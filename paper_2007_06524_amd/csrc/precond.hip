@@ -1203,6 +1203,7 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
     };
     double best = 1e300;
     int best_cfg = -1;
+    std::vector<double> times(ncfg, 1e300);
     for (int c = 0; c < ncfg; ++c) {
       GemmArgs gd = g;
       if (sixteen && stg == 2) {
@@ -1253,11 +1254,16 @@ int autotune_precond(kp_context* ctx, kp_precond* pc, int nsys, int reps, kp_til
         e.ms = avg;
       }
       ++n;
+      times[c] = avg;
       if (avg < best) {
         best = avg;
         best_cfg = c;
       }
     }
+    // The two block orders of one tile shape within 1 % of each other (timing
+    // noise): take the XCD-grouped one, which reads each column tile of the
+    // data operand from HBM once instead of once per row tile.
+    if (best_cfg >= 0 && best_cfg < ntile && times[best_cfg + ntile] <= 1.01 * best) best_cfg += ntile;
     tiles[stg] = best_cfg;
   }
   if (count) *count = n;
